@@ -1,0 +1,62 @@
+"""numpy brute force for tiny lattices (test-only, independent of the oracle).
+
+``action`` evaluates s = sum_n sum_{mu<nu} Re Tr[1 - Z^*_{mu nu}(n) P_{mu nu}(n)]
+(sec. 3.1, g0^2 S_W / 2) with whole-array shifts; ``fd_force_components``
+differentiates it numerically along the eight su(3) generators of a link, so
+the oracle's analytic force can be checked against the action it derives
+from without reusing any of its staple algebra.
+"""
+
+import numpy as np
+
+from fields import OMEGA, coords, su3_generators
+
+
+def _dag(x):
+    return np.conj(np.swapaxes(x, -1, -2))
+
+
+def _shift(A, mu):
+    """A(n + mu_hat) in canonical axis order (axis 3 - mu is n_mu)."""
+    return np.roll(A, -1, axis=3 - mu)
+
+
+def action(U, dims, twist=(1, 0, 0, 0, 0, 0), base=(0, 0, 0, 0)):
+    n = coords(dims)
+    s = 0.0
+    k = 0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            P = U[..., mu, :, :] @ _shift(U[..., nu, :, :], mu) \
+                @ _dag(_shift(U[..., mu, :, :], nu)) @ _dag(U[..., nu, :, :])
+            tr = np.trace(P, axis1=-2, axis2=-1)
+            z = np.ones(tr.shape, complex)
+            if twist[k] % 3:
+                on = (n[mu] == base[mu]) & (n[nu] == base[nu])
+                z[on] = OMEGA ** (twist[k] % 3)
+            s += np.sum(3.0 - np.real(np.conj(z) * tr))
+            k += 1
+    return s
+
+
+def expm_small(A, terms=30):
+    out = np.eye(3, dtype=complex)
+    term = np.eye(3, dtype=complex)
+    for k in range(1, terms):
+        term = term @ A / k
+        out = out + term
+    return out
+
+
+def fd_force_components(U, dims, site, mu, twist=(1, 0, 0, 0, 0, 0), h=1e-4):
+    """d/ds s(exp(s T^a) U_mu(site)) at s = 0 for a = 1..8 (central differences)."""
+    T = su3_generators()
+    d = np.zeros(8)
+    for a in range(8):
+        vals = []
+        for sgn in (+1, -1):
+            V = U.copy()
+            V[site + (mu,)] = expm_small(sgn * h * T[a]) @ U[site + (mu,)]
+            vals.append(action(V, dims, twist))
+        d[a] = (vals[0] - vals[1]) / (2 * h)
+    return d

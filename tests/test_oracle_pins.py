@@ -1,0 +1,328 @@
+"""Pins of the FP64 CPU oracle against closed forms, symmetries and brute force.
+
+Each test fixes something the oracle could plausibly get wrong (a twist
+factor on the wrong plaquette or leaf, a wrong sign or index in the staples,
+the force normalisation, the RK3 coefficients, the clover normalisation, the
+orientation of Q) using a fact the paper or the mathematics fixes
+independently of the oracle's own code.  Paper passages: the twisted Wilson
+action, twist factors, clover G and Q of sec. 3.1; the twist algebra
+Gamma_1 Gamma_2 = Z_12 Gamma_2 Gamma_1 of sec. 1.
+"""
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+import brute
+import fields
+from paper_2107_03747_amd import gen
+
+TW = oracle.PAPER_TWIST
+NOTW = (0, 0, 0, 0, 0, 0)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+# ----------------------------------------------------------------------------
+# exponential: a special case that reduces to a library routine
+
+@pytest.mark.parametrize("scale", [1e-3, 0.05, 0.7, 3.0, 12.0])
+def test_expm_matches_scipy(scale):
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        A = rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3))
+        A = 0.5 * (A - A.conj().T)
+        A -= np.trace(A) / 3 * np.eye(3)
+        A *= scale / np.linalg.norm(A)
+        ref = scipy.linalg.expm(A)
+        got = oracle.expm(A)
+        assert np.abs(got - ref).max() <= 2e-14 * max(1.0, np.abs(ref).max()) * (1 + scale)
+
+
+def test_expm_general_matrix():
+    rng = np.random.default_rng(8)
+    A = rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3))
+    assert np.allclose(oracle.expm(A), scipy.linalg.expm(A), rtol=1e-13, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# T7: twist-eater (zero action) -- pins every twist factor of action, force, leaves
+
+@pytest.mark.parametrize("dims", [(4, 4, 12, 12), (3, 3, 5, 4), (2, 2, 6, 6)])
+def test_twist_eater_zero_action(dims):
+    U = fields.twist_eater(dims)
+    m = oracle.measure(U, dims, TW)
+    assert abs(m["plaq"] - 1) < 1e-14
+    assert abs(m["action"]) < 1e-10
+    assert abs(m["E"]) < 1e-28
+    assert abs(m["Q"]) < 1e-14
+    assert np.abs(oracle.force(U, dims, TW)).max() < 1e-14
+    U0 = U.copy()
+    oracle.flow(U, dims, 0.02, 0.1, 0.05, twist=TW)
+    assert np.abs(U - U0).max() < 1e-14
+
+
+def test_twist_eater_conjugate_twist():
+    """k = 2 twist (charge conjugate of k = 1) is eaten by the conjugate matrices."""
+    dims = (3, 3, 5, 4)
+    U = fields.twist_eater(dims, k=2)
+    m = oracle.measure(U, dims, (2, 0, 0, 0, 0, 0))
+    assert abs(m["E"]) < 1e-28 and abs(m["plaq"] - 1) < 1e-14
+    # ... and is NOT a zero-action field for the k = 1 twist
+    m1 = oracle.measure(U, dims, TW)
+    assert m1["E"] > 1e-3
+
+
+def test_twist_eater_gauge_transformed():
+    dims = (3, 3, 6, 6)
+    Lam = fields.su3_field(fields.shape(dims), seed=11)
+    U = fields.gauge_transform(fields.twist_eater(dims), Lam)
+    m = oracle.measure(U, dims, TW)
+    assert abs(m["E"]) < 1e-26 and abs(m["plaq"] - 1) < 1e-14 and abs(m["Q"]) < 1e-14
+    assert np.abs(oracle.force(U, dims, TW)).max() < 1e-13
+
+
+def test_identity_in_twisted_box_action():
+    """Unit links in the twisted box: only the d2*d3 twisted plaquettes deviate,
+    each by Re Tr[1 - w^*] = 3 + 3/2."""
+    dims = (4, 4, 12, 12)
+    m = oracle.measure(fields.identity(dims), dims, TW)
+    assert rel(m["action"], 4.5 * 12 * 12) < 1e-14
+    assert rel(m["plaq"], 1 - 4.5 * 144 / (18 * 4 * 4 * 144)) < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# constant abelian flux: closed forms for E, Q (normalisation and sign), plaquette
+
+@pytest.mark.parametrize("dims,m01,m23", [((4, 4, 12, 12), 1, 1), ((6, 4, 6, 8), 2, -1),
+                                          ((4, 6, 5, 5), -1, 3)])
+def test_flux_closed_form(dims, m01, m23):
+    U, p01, p23 = fields.flux_field(dims, m01, m23)
+    V = np.prod(dims)
+    m = oracle.measure(U, dims, NOTW)
+    # G_01 = sin(p01 H), G_23 = sin(p23 H), H = diag(1,-1,0)
+    assert rel(m["E"], 2 * np.sin(p01) ** 2 + 2 * np.sin(p23) ** 2) < 1e-13
+    assert rel(m["Q"], V * 2 * np.sin(p01) * np.sin(p23) / (4 * np.pi ** 2)) < 1e-12
+    plaq = (12 + (2 * np.cos(p01) + 1) + (2 * np.cos(p23) + 1)) / 18
+    assert abs(m["plaq"] - plaq) < 1e-14
+    # a constant field strength is a stationary point of the action
+    assert np.abs(oracle.force(U, dims, NOTW)).max() < 1e-13
+
+
+def test_flux_charge_approaches_integer():
+    """Q -> 2 m01 m23 as the flux gets smoother (continuum instanton number of
+    the H = diag(1,-1,0) embedding)."""
+    dims = (16, 16, 16, 16)
+    U, _, _ = fields.flux_field(dims, 1, 1)
+    m = oracle.measure(U, dims, NOTW)
+    assert abs(m["Q"] - 2) < 2e-3
+
+
+# ----------------------------------------------------------------------------
+# T11: single Fourier mode -- force normalisation, meaning of t, RK3 stability polynomial
+
+@pytest.mark.parametrize("rho,pn", [(3, (1, 1, 1, 0)), (0, (0, 1, 2, 3)), (2, (1, 0, 0, 2))])
+def test_single_mode_energy_and_decay(rho, pn):
+    dims = (4, 4, 12, 12)
+    p = np.array([2 * np.pi * pn[m] / dims[m] for m in range(4)])
+    alpha = 1e-3
+    U = fields.single_mode(dims, alpha, p, rho)
+    E0 = 0.25 * alpha ** 2 * sum(np.sin(p[m]) ** 2 for m in range(4) if m != rho)
+    eps = 0.04
+    rows = oracle.flow(U, dims, eps, 0.2, eps, twist=NOTW)
+    assert rel(rows[0, 1], E0) < 1e-5
+    phat2 = sum(4 * np.sin(p[m] / 2) ** 2 for m in range(4))
+    z = -eps * phat2
+    R = 1 + z + z * z / 2 + z ** 3 / 6
+    for r in rows:
+        k = round(r[0] / eps)
+        assert rel(r[1], E0 * R ** (2 * k)) < 1e-5
+
+
+# ----------------------------------------------------------------------------
+# T12: analytic force vs finite differences of the action (tiny lattices)
+
+@pytest.mark.parametrize("dims,twist", [((2, 2, 4, 4), TW), ((3, 3, 4, 3), TW),
+                                        ((3, 3, 4, 3), (1, 0, 2, 1, 0, 2))])
+def test_force_matches_action_derivative(dims, twist):
+    U = gen.haar(dims, seed=21).numpy().copy()
+    F = oracle.force(U, dims, twist)
+    T = fields.su3_generators()
+    # brute-force action agrees with the oracle's
+    assert rel(brute.action(U, dims, twist), oracle.measure(U, dims, twist)["action"]) < 1e-12
+    rng = np.random.default_rng(3)
+    d0, d1, d2, d3 = dims
+    sites = [(0, 0, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1), (1, 1, 0, 0), (0, 0, 1, 1)]
+    sites += [tuple(int(rng.integers(d)) for d in (d3, d2, d1, d0)) for _ in range(3)]
+    for site in sites:
+        for mu in range(4):
+            fd = brute.fd_force_components(U, dims, site, mu, twist)
+            an = np.array([np.trace(T[a] @ F[site + (mu,)]).real for a in range(8)])
+            assert np.abs(fd - an).max() < 1e-7, (site, mu, fd, an)
+
+
+def test_force_is_traceless_antihermitian():
+    dims = (3, 3, 4, 4)
+    U = gen.haar(dims, seed=5).numpy().copy()
+    F = oracle.force(U, dims, TW)
+    assert np.abs(F + np.conj(np.swapaxes(F, -1, -2))).max() < 1e-14
+    assert np.abs(np.trace(F, axis1=-2, axis2=-1)).max() < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# T1: gauge invariance of observables and covariance of the flow
+
+def test_gauge_invariance_and_covariance():
+    dims = (4, 4, 6, 6)
+    U = gen.near_identity(dims, 0.5, seed=31).numpy().copy()
+    Lam = fields.su3_field(fields.shape(dims), seed=32)
+    Ug = fields.gauge_transform(U, Lam)
+    a = oracle.flow(U, dims, 0.02, 0.1, 0.02, twist=TW)
+    b = oracle.flow(Ug, dims, 0.02, 0.1, 0.02, twist=TW)
+    assert np.allclose(a[:, 1], b[:, 1], rtol=1e-12, atol=0)
+    assert np.allclose(a[:, 3], b[:, 3], rtol=1e-14, atol=0)
+    assert np.allclose(a[:, 4], b[:, 4], rtol=0, atol=1e-12)
+    assert np.abs(fields.gauge_transform(U, Lam) - Ug).max() < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# T2: centre symmetry
+
+@pytest.mark.parametrize("mu,c", [(0, 0), (1, 2), (3, 1)])
+def test_centre_symmetry(mu, c):
+    dims = (4, 4, 6, 6)
+    U = gen.near_identity(dims, 0.6, seed=41).numpy().copy()
+    n = fields.coords(dims)
+    V = U.copy()
+    V[..., mu, :, :][n[mu] == c] *= fields.OMEGA
+    a = oracle.flow(U.copy(), dims, 0.02, 0.06, 0.02, twist=TW)
+    b = oracle.flow(V.copy(), dims, 0.02, 0.06, 0.02, twist=TW)
+    assert np.allclose(a[:, 1:], b[:, 1:], rtol=1e-12, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# T3/T4: twist relocation and translations
+
+def test_twist_relocation():
+    """Multiplying U_1 on the column (n0, n1) = (0, 0) by Z_01 = w moves the
+    twisted plaquette from (0, 0) to (d0-1, 0): all observables and the flow
+    are unchanged when the twist site moves with it."""
+    dims = (4, 4, 6, 6)
+    U = gen.near_identity(dims, 0.6, seed=51).numpy().copy()
+    n = fields.coords(dims)
+    V = U.copy()
+    V[..., 1, :, :][(n[0] == 0) & (n[1] == 0)] *= fields.OMEGA
+    a = oracle.flow(U.copy(), dims, 0.02, 0.06, 0.02, twist=TW, base=(0, 0, 0, 0))
+    b = oracle.flow(V.copy(), dims, 0.02, 0.06, 0.02, twist=TW, base=(dims[0] - 1, 0, 0, 0))
+    assert np.allclose(a[:, 1:], b[:, 1:], rtol=1e-12, atol=1e-13)
+    # ... while keeping the twist where it was changes the physics
+    c = oracle.measure(V.copy(), dims, TW)
+    assert abs(c["action"] - a[0, 5]) > 1.0
+
+
+@pytest.mark.parametrize("mu", [0, 1, 2, 3])
+def test_translation(mu):
+    dims = (4, 4, 6, 6)
+    U = gen.near_identity(dims, 0.6, seed=61).numpy().copy()
+    V = np.ascontiguousarray(np.roll(U, 1, axis=3 - mu))   # V(n) = U(n - mu)
+    base = [0, 0, 0, 0]
+    base[mu] = 1
+    a = oracle.flow(U.copy(), dims, 0.02, 0.04, 0.02, twist=TW)
+    b = oracle.flow(V.copy(), dims, 0.02, 0.04, 0.02, twist=TW, base=base)
+    assert np.allclose(a[:, 1:], b[:, 1:], rtol=1e-12, atol=1e-13)
+    if mu >= 2:   # untwisted directions: no relocation needed
+        c = oracle.flow(V.copy(), dims, 0.02, 0.04, 0.02, twist=TW)
+        assert np.allclose(a[:, 1:], c[:, 1:], rtol=1e-12, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# T5: reflection flips Q;  T6: charge conjugation with the conjugate twist
+
+def test_reflection_flips_charge():
+    dims = (4, 4, 6, 6)
+    U = gen.near_identity(dims, 0.8, seed=71).numpy().copy()
+    R = np.ascontiguousarray(fields.reflect3(U))
+    a = oracle.measure(U, dims, TW)
+    b = oracle.measure(R, dims, TW)
+    assert rel(b["E"], a["E"]) < 1e-12 and abs(b["plaq"] - a["plaq"]) < 1e-14
+    assert abs(a["Q"]) > 1e-3
+    assert abs(b["Q"] + a["Q"]) < 1e-12
+    Uf, _, _ = fields.flux_field((4, 4, 6, 6), 1, 1)
+    qa = oracle.measure(Uf, (4, 4, 6, 6), NOTW)["Q"]
+    qb = oracle.measure(np.ascontiguousarray(fields.reflect3(Uf)), (4, 4, 6, 6), NOTW)["Q"]
+    assert qa > 0.5 and abs(qa + qb) < 1e-12
+
+
+def test_reflection_symmetric_field_has_zero_charge():
+    """U_2 = U_3 = 1 and no n2, n3 dependence -> Q = 0 exactly."""
+    dims = (4, 4, 3, 3)
+    U = fields.identity(dims)
+    u01 = gen.near_identity((4, 4, 1, 1), 0.9, seed=72).numpy()
+    U[..., 0:2, :, :] = u01[..., 0:2, :, :]
+    m = oracle.measure(U, dims, TW)
+    assert abs(m["Q"]) < 1e-15 and m["E"] > 1e-3
+
+
+def test_charge_conjugation():
+    dims = (4, 4, 6, 6)
+    U = gen.near_identity(dims, 0.7, seed=81).numpy().copy()
+    a = oracle.flow(U.copy(), dims, 0.02, 0.04, 0.02, twist=TW)
+    b = oracle.flow(np.ascontiguousarray(U.conj()), dims, 0.02, 0.04, 0.02,
+                    twist=(2, 0, 0, 0, 0, 0))
+    assert np.allclose(a[:, 1:], b[:, 1:], rtol=1e-12, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# T8, T9: group manifold and monotone action along the flow
+
+def test_flow_stays_on_group_and_action_decreases():
+    dims = (4, 4, 6, 6)
+    U = gen.haar(dims, seed=91).numpy().copy()
+    s_prev = oracle.measure(U, dims, TW)["action"]
+    for _ in range(6):
+        oracle.rk3_step(U, dims, 0.02, TW)
+        s = oracle.measure(U, dims, TW)["action"]
+        assert s <= s_prev * (1 + 1e-12)
+        s_prev = s
+    uu, det = fields.unitarity_defect(U)
+    assert uu < 1e-13 and det < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# T10: RK3 global error ~ eps^3
+
+def test_rk3_third_order():
+    dims = (3, 3, 4, 4)
+    U0 = gen.near_identity(dims, 0.9, seed=101).numpy()
+    T = 0.2
+
+    def flow_to(eps):
+        U = U0.copy()
+        for _ in range(round(T / eps)):
+            oracle.rk3_step(U, dims, eps, TW)
+        return U
+
+    ref = flow_to(T / 256)
+    errs = [np.abs(flow_to(T / n) - ref).max() for n in (4, 8, 16)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 6.5 < r1 < 9.5 and 6.5 < r2 < 9.5, errs
+
+
+# ----------------------------------------------------------------------------
+# measurement schedule
+
+def test_schedule_rows():
+    dims = (2, 2, 3, 3)
+    U = fields.twist_eater(dims)
+    rows = oracle.flow(U, dims, 0.01, 0.405, 0.1, twist=TW)
+    assert np.allclose(rows[:, 0], [0, 0.1, 0.2, 0.3, 0.4, 0.405], atol=1e-12)
+    rows = oracle.flow(U, dims, 0.01, 0.32, 0.02, twist=TW)
+    assert len(rows) == 17 and abs(rows[-1, 0] - 0.32) < 1e-12
+    rows = oracle.flow(U, dims, 0.01, 0.05, 0.0, t0=0.02, twist=TW)
+    assert len(rows) == 1 and abs(rows[0, 0] - 0.05) < 1e-12
+    rows = oracle.flow(U, dims, 0.01, 0.3, 0.0, t0=0.3, twist=TW)
+    assert len(rows) == 1 and abs(rows[0, 0] - 0.3) < 1e-12
+    assert np.allclose(rows[:, 2], rows[:, 0] ** 2 * rows[:, 1])
