@@ -1,0 +1,290 @@
+"""Benchmark: twisted Wilson flow throughput on one MI355X.
+
+One step = one pass of the whole hot path over one batch: ingest of the
+canonical FP64 links of every configuration (pack into device storage +
+SU(3) check) followed by the full flow of the batch to its t_end with RK3
+steps of eps = 0.01, FP64 measurements of t^2 E, plaquette and Q every 0.1
+and at t_end, all stage launches of the batch captured in one HIP graph.
+
+Default workload (ensemble batch): 64 configurations of 8x8x24x24, 16 of
+6x6x18x18 and 16 of 10x10x30x30, twist n_01 = 1, seeded near-identity links
+exp(i eps H) with eps in {0.2, 0.3, 0.4}, flowed to c = 0.3 (t_end =
+c^2 L^2 / 8), FP32 storage with 12-real links, FP64 reunitarisation every
+10 steps.  The same batch is also flowed with the plain FP64 path.
+`--workload large` runs one 32x32x96x96 box (t_end 11.52, measured every 0.1).
+
+Prints one JSON line (metric, value = site-updates/s, roofline, cpu_baseline).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "flowed site-updates/s + HBM GB/s (FP32 batched vs FP64 plain) at t^2E err<=1e-5"
+EPS = 0.01
+HBM_PEAK_GBS = 8000.0
+# Non-packed FP32 (and FP64) vector peak: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def batch_workload():
+    """(dims, link-eps, seed, t_end) per configuration."""
+    cfgs = []
+    j = 0
+    for L, count in ((8, 64), (6, 16), (10, 16)):
+        for _ in range(count):
+            cfgs.append(((L, L, 3 * L, 3 * L), (0.2, 0.3, 0.4)[j % 3], 4000 + j,
+                         0.09 * L * L / 8))
+            j += 1
+    return cfgs
+
+
+def large_workload():
+    return [((32, 32, 96, 96), None, 5, 0.09 * 32 * 32 / 8)]
+
+
+def n_steps(t_end, t0=0.0):
+    n = 0
+    while t0 + (n + 1) * EPS <= t_end + 1e-12:
+        n += 1
+    return n + (1 if t_end - (t0 + n * EPS) > 1e-12 else 0)
+
+
+# Algorithmic work per site per RK3 step (3 stages) -- see the design doc.
+def bytes_per_site_step(storage):
+    ne, cb = (6, 8) if storage == "f32c12" else ((9, 8) if storage == "f32" else (9, 16))
+    links = 3 * 2 * 4 * ne * cb           # read + write every stage
+    x = (1 + 2 + 1) * 4 * 4 * cb          # X: write, read+write, read
+    return links + x
+
+
+def flops_per_site_step(storage, variant):
+    mm = 198.0                             # 3x3 complex product: 27 cmul + 18 cadd
+    if variant in ("site", "site_xcd"):
+        per_stage = 46 * mm                # 6 shared plaquettes (3 each) + 12 lower (2) + 4
+        loads = 4 + 12 + 36                # link loads per site (row-2 rebuilds for C12)
+    else:
+        per_stage = 52 * mm                # 4 links x (6 staples x 2 + 1)
+        loads = 4 * (1 + 6 * 3)
+    per_link = 40 + 16 + 300 + (2 * 3 * 3 * 8 - 12 if storage == "f32c12" else mm)
+    rebuild = 42 * loads if storage == "f32c12" else 0
+    return 3 * (per_stage + 4 * per_link + rebuild)
+
+
+def make_inputs(cfgs, device):
+    from paper_2107_03747_amd import gen
+    out = []
+    for dims, e, seed, _ in cfgs:
+        if e is None:
+            out.append(gen.haar(dims, seed, device=device))
+        else:
+            out.append(gen.near_identity(dims, e, seed, device=device))
+    return out
+
+
+def time_flows(tgf, torch, cfgs, inputs, storage, steps, warmup, flags=0, reunit=10,
+               autotune=True):
+    t_end = [c[3] for c in cfgs]
+    f = tgf.Flow([c[0] for c in cfgs], storage)
+    f.load_all(inputs)
+    if autotune:
+        f.autotune(None)
+
+    def one():
+        f.load_all(inputs)
+        return f.flow(EPS, t_end, 0.1, reunit, flags)
+
+    rows = None
+    for _ in range(warmup):
+        rows = one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rows = one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    return f, rows, dt
+
+
+def cpu_baseline(cfgs, inputs, gpu_rows, target_s=12.0):
+    """The FP64 oracle on a bounded sample: the first configuration of the
+    workload, flowed from t = 0 for as many steps as fit in ~target_s."""
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    dims = cfgs[0][0]
+    U0 = inputs[0].cpu().numpy().copy()
+    V = int(np.prod(dims))
+    # probe the rate on one step, then size the sample
+    U = U0.copy()
+    t = time.perf_counter()
+    oracle.rk3_step(U, dims, EPS)
+    probe = time.perf_counter() - t
+    nst = int(max(2, min(n_steps(cfgs[0][3]), target_s / max(probe, 1e-6))))
+    # keep the sample on the 0.1 measurement grid when possible (parity sample)
+    if nst >= 10:
+        nst = nst // 10 * 10
+    U = U0.copy()
+    t = time.perf_counter()
+    rows = oracle.flow(U, dims, EPS, nst * EPS, 0.0)
+    dt = time.perf_counter() - t
+    err = None
+    tt = rows[-1, 0]
+    k = [r for r in range(gpu_rows.shape[0]) if abs(gpu_rows[r, 0, 0] - tt) < 1e-9]
+    if k:
+        g = gpu_rows[k[0], 0, 2]
+        err = abs(g - rows[-1, 2]) / abs(rows[-1, 2])
+    return {
+        "value": V * nst / dt,
+        "unit": "site-updates/s",
+        "cores": oracle.get_threads(),
+        "kind": "oracle",
+        "sample": f"config 0 ({'x'.join(map(str, dims))}), {nst} RK3 steps of eps={EPS} "
+                  f"from t=0 plus one measurement, FP64, {dt:.1f} s",
+    }, err, float(tt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=("batch", "large"), default="batch")
+    ap.add_argument("--storage", choices=("f32c12", "f32", "f64"), default="f32c12")
+    ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2107_03747_amd import tgf
+
+    cfgs = batch_workload() if args.workload == "batch" else large_workload()
+    log(f"generating {len(cfgs)} configurations on the GPU")
+    inputs = make_inputs(cfgs, "cuda")
+    torch.cuda.synchronize()
+    site_updates = sum(math.prod(c[0]) * n_steps(c[3]) for c in cfgs)
+    sites = sum(math.prod(c[0]) for c in cfgs)
+
+    log(f"timing {args.storage}: {args.warmup} warmup + {args.steps} steps")
+    f, rows, dt = time_flows(tgf, torch, cfgs, inputs, args.storage, args.steps, args.warmup,
+                             autotune=args.variant is None)
+    if args.variant is not None:
+        f.set_variant(args.variant)
+    variant = tgf.variant_names()[f.variant]
+    value = site_updates / dt
+
+    # kernel durations with HIP events on the library's stream (same launches)
+    log("kernel timing pass")
+    f.load_all(inputs)
+    f.flow(EPS, [c[3] for c in cfgs], 0.1, 10, tgf.TGF_TIMING)
+    tm = f.timing()
+    stage_avg_ms = tm["stage_ms"] / tm["stage_launches"]
+    gbs = tm["stage_bytes"] / (tm["stage_ms"] * 1e-3) / 1e9
+    su_per_s_kernel = tm["stage_site_updates"] / (tm["stage_ms"] * 1e-3)
+    fl = flops_per_site_step(args.storage, variant)
+    tflops = su_per_s_kernel * fl / 1e12
+    hbm_frac = gbs / HBM_PEAK_GBS
+    alu_frac = tflops / ALU_PEAK_TFLOPS
+    per_launch_bytes = tm["stage_bytes"] / tm["stage_launches"]
+    roofline = {
+        "kernel": f"stage_{'site' if 'site' in variant else 'link'}_kernel "
+                  f"<{'float' if args.storage != 'f64' else 'double'}, "
+                  f"{6 if args.storage == 'f32c12' else 9}>",
+        "bound": "alu" if alu_frac >= hbm_frac else "hbm",
+        "achieved": round(tflops if alu_frac >= hbm_frac else gbs, 3),
+        "peak": round(ALU_PEAK_TFLOPS, 1) if alu_frac >= hbm_frac else HBM_PEAK_GBS,
+        "unit": "TFLOP/s" if alu_frac >= hbm_frac else "GB/s",
+        "frac": round(max(alu_frac, hbm_frac), 4),
+        "traffic": None,
+        "hbm_gbs": round(gbs, 1),
+        "hbm_frac": round(hbm_frac, 4),
+        "alu_tflops": round(tflops, 2),
+        "alu_frac": round(alu_frac, 4),
+        "avg_launch_ms": round(stage_avg_ms, 4),
+        "launches": int(tm["stage_launches"]),
+        "bytes_per_launch": round(per_launch_bytes),
+        "bytes_per_site_step": bytes_per_site_step(args.storage),
+        "flops_per_site_step": round(fl),
+        "measure_ms_per_flow": round(tm["measure_ms"], 3),
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("ensemble batch: 64 x 8x8x24x24 + 16 x 6x6x18x18 + 16 x 10x10x30x30, "
+                         "twist n01=1, near-identity links eps {0.2,0.3,0.4}, flow to c=0.3")
+                        if args.workload == "batch" else
+                        "large box 32x32x96x96, twist n01=1, Haar links, flow to c=0.3",
+            "n_configs": len(cfgs),
+            "sites": sites,
+            "site_updates_per_step": site_updates,
+            "storage": args.storage,
+            "eps": EPS,
+            "meas_dt": 0.1,
+            "reunit_every": 10,
+            "variant": variant,
+            "hip_graph": True,
+        },
+        "roofline": roofline,
+    }
+
+    if not args.no_fp64 and args.storage != "f64":
+        log("timing FP64 plain path on the same workload")
+        del f
+        torch.cuda.empty_cache()
+        k64 = max(1, args.steps // 3)
+        f64, rows64, dt64 = time_flows(tgf, torch, cfgs, inputs, "f64", k64, 1)
+        pos = rows64[:, :, 0] > 0
+        rel = np.abs(rows[:, :, 2] - rows64[:, :, 2])[pos] / np.abs(rows64[:, :, 2][pos])
+        out["fp64_plain"] = {"value": round(site_updates / dt64, 1), "unit": "site-updates/s",
+                             "ms_per_step": round(dt64 * 1e3, 3), "steps": k64,
+                             "variant": tgf.variant_names()[f64.variant]}
+        out["speedup_vs_fp64_plain"] = round(dt64 / dt, 3)
+        out["t2E_max_rel_err_vs_fp64_gpu"] = float(rel.max())
+        del f64
+
+    if not args.no_cpu:
+        log("CPU baseline (oracle)")
+        cb, err, tt = cpu_baseline(cfgs, inputs, rows)
+        out["cpu_baseline"] = cb
+        out["t2E_rel_err_vs_oracle_sample"] = err
+        out["t2E_oracle_sample_t"] = tt
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

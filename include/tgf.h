@@ -1,0 +1,190 @@
+/*
+ * tgf.h -- C ABI of libtgf.so: twisted Wilson flow of SU(3) lattice gauge
+ * fields on MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem (Bribian, Dasilva
+ * Golan, Garcia Perez, Ramos, arXiv 2107.03747, sec. 3.1): SU(3) links
+ * U_mu(n) on an L x L x 3L x 3L torus whose short-short plane carries
+ * twisted boundary conditions through the factors Z_{mu nu}(n) of the Wilson
+ * action; the links are evolved with the Wilson-flow discretisation of the
+ * gradient flow equation (sec. 1) to flow time t, and at t the clover energy
+ * density E_cl (eq. gmunu), t^2 <E>, the plaquette and the topological charge
+ * Q (eq. qlatt) are measured.
+ *
+ * Conventions
+ *   - Directions mu = 0..3 are the paper's 1..4.  The twisted plane of the
+ *     paper is (0, 1) here; dims = {d0, d1, d2, d3} = {L, L, 3L, 3L}.  Any
+ *     d_mu >= 2 is accepted.
+ *   - twist[6] = n_01, n_02, n_03, n_12, n_13, n_23 in {0, 1, 2}; the paper's
+ *     setting is {1,0,0,0,0,0}.  Z_{mu nu}(n) = exp(2 pi i n_{mu nu}/3) when
+ *     n_mu = n_nu = 0 (the 0-based form of the paper's x_1 = x_2 = 1) and 1
+ *     elsewhere; Z_{nu mu} = Z_{mu nu}^*.
+ *   - Canonical link layout (every links_dev argument): complex128 (two
+ *     doubles, re then im), C-contiguous [d3][d2][d1][d0][4][3][3], site
+ *     index n0 + d0*(n1 + d1*(n2 + d2*n3)), row-major 3x3, device memory.
+ *   - Flow: Luscher's three-stage Runge-Kutta scheme with force
+ *     F = -P_ah(Omega) (P_ah = traceless anti-Hermitian part, Omega the
+ *     twisted staple sum), step eps, a shortened last step to reach t_end.
+ *   - Observables (FP64, tgf_obs): E = site average of
+ *     e(n) = 1/2 sum_{mu,nu} Tr G_{mu nu} G_{mu nu}; t2E = t^2 E;
+ *     plaq = (1/18V) sum_n sum_{mu<nu} Re Tr[Z^* P_{mu nu}(n)];
+ *     Q = (1/16 pi^2) sum_n Tr G G~ with eps_{0123} = +1;
+ *     action = sum_n sum_{mu<nu} Re Tr[1 - Z^* P_{mu nu}(n)].
+ *
+ * Ownership: the caller owns all device memory -- the workspace (one
+ * allocation of tgf_workspace_bytes), every link buffer -- and the HIP
+ * stream.  The library never allocates or frees device memory; a context
+ * owns only host state (including a pinned staging buffer) and its cached
+ * HIP graph.
+ *
+ * Ordering and threading: every call enqueues on the context's stream.
+ * tgf_load_links*, tgf_measure, tgf_flow and tgf_unitarity synchronise that
+ * stream before returning.  A context is not thread-safe; contexts on
+ * different streams are independent.
+ *
+ * Errors: every call returns a tgf_status and never aborts or throws.
+ * Arguments are validated on the host before anything is enqueued; on a
+ * validation error nothing is enqueued and the context is unchanged.
+ * tgf_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef TGF_H
+#define TGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TGF_OK = 0,
+    TGF_E_INVAL = -1,       /* bad argument (dims, twist, eps, t, pointer, cfg index) */
+    TGF_E_SIZE = -2,        /* workspace or row buffer too small */
+    TGF_E_HIP = -3,         /* a HIP runtime call failed */
+    TGF_E_NOT_SU3 = -4,     /* loaded links not in SU(3) within 1e-10, or non-finite */
+    TGF_E_NONFINITE = -5,   /* a measured sum was not finite; links are undefined */
+    TGF_E_STATE = -6,       /* call not valid in this state (e.g. flow before load) */
+    TGF_E_UNSUPPORTED = -7  /* option not supported for this storage */
+} tgf_status;
+
+/* Device storage of the flowed links and RK accumulator. */
+typedef enum {
+    TGF_F64_FULL = 0,   /* FP64, all 9 complex entries (the plain path) */
+    TGF_F32_FULL = 1,   /* FP32, all 9 complex entries */
+    TGF_F32_C12 = 2     /* FP32, rows 0 and 1 only; row 2 = conj(row0 x row1) */
+} tgf_storage;
+
+typedef struct {
+    int32_t dims[4];    /* d0, d1 (twisted plane), d2, d3; each >= 2 */
+    int32_t twist[6];   /* n01, n02, n03, n12, n13, n23 in {0,1,2} */
+} tgf_geom;
+
+typedef struct {
+    double t, E, t2E, plaq, Q, action;
+} tgf_obs;
+
+/* tgf_flow_params.flags */
+#define TGF_NO_GRAPH 1u   /* launch kernels directly instead of a cached HIP graph
+                             (always the case on the null stream) */
+#define TGF_TIMING 2u     /* time every kernel with HIP events (implies NO_GRAPH) */
+
+typedef struct {
+    double eps;            /* step size, > 0 */
+    const double *t_end;   /* [n_cfg] host array, t_end[c] >= current t of cfg c */
+    double meas_dt;        /* measurement grid spacing; 0 = only at t_end */
+    int32_t reunit_every;  /* FP32 storages: reunitarise in FP64 every R steps (0 = never);
+                              ignored for TGF_F64_FULL */
+    uint32_t flags;        /* TGF_NO_GRAPH | TGF_TIMING */
+} tgf_flow_params;
+
+/* Kernel time of the last tgf_flow run with TGF_TIMING. */
+typedef struct {
+    double stage_ms;          /* total duration of the RK stage kernels */
+    int64_t stage_launches;   /* number of RK stage launches */
+    double stage_bytes;       /* algorithmic HBM bytes moved by those launches */
+    double stage_site_updates;/* site-stage updates / 3 (= site-updates) */
+    double measure_ms;        /* measurement + reduction kernels */
+    int64_t measure_launches;
+} tgf_timing;
+
+/* Maximum rows (measurement times) one tgf_flow call can return per config. */
+#define TGF_MAX_ROWS 4096
+
+typedef struct tgf_ctx tgf_ctx;
+
+/* Bytes of device workspace needed for n_cfg configurations with geometries
+ * geoms[n_cfg] in storage st.  Returns 0 on invalid arguments. */
+size_t tgf_workspace_bytes(int32_t n_cfg, const tgf_geom *geoms, tgf_storage st);
+
+/* Create a context over caller-owned device memory workspace_dev (at least
+ * tgf_workspace_bytes, 256-byte aligned) and the HIP stream hip_stream
+ * (hipStream_t; NULL = the null stream).  Configurations start unloaded. */
+tgf_status tgf_create(tgf_ctx **out, int32_t n_cfg, const tgf_geom *geoms, tgf_storage st,
+                      void *workspace_dev, size_t workspace_bytes, void *hip_stream);
+
+/* Copy links of configuration cfg from canonical device memory into the
+ * context's storage and set its flow time to t0.  The input is checked:
+ * max |U U^+ - 1| and |det U - 1| above 1e-10 (or any non-finite entry)
+ * return TGF_E_NOT_SU3 and leave cfg unloaded.  Synchronises. */
+tgf_status tgf_load_links(tgf_ctx *c, int32_t cfg, const void *links_dev, double t0);
+
+/* Same for every configuration at once: links_dev[n_cfg] (host array of
+ * device pointers), t0[n_cfg] (host).  One check, one synchronisation. */
+tgf_status tgf_load_links_all(tgf_ctx *c, const void *const *links_dev, const double *t0);
+
+/* Write the current links of cfg in canonical layout (FP64; C12 rebuilds row
+ * 2).  Enqueued only; the caller synchronises the stream. */
+tgf_status tgf_store_links(tgf_ctx *c, int32_t cfg, void *links_dev);
+
+/* Current flow time of cfg. */
+tgf_status tgf_get_time(tgf_ctx *c, int32_t cfg, double *t);
+
+/* Measure every loaded configuration at its current flow time:
+ * out_host[n_cfg].  Synchronises. */
+tgf_status tgf_measure(tgf_ctx *c, tgf_obs *out_host);
+
+/* Flow every configuration from its current t to p->t_end[cfg].  Rows go to
+ * rows_host[max_rows][n_cfg] (row-major, config fastest): a row at the start
+ * time if it lies on the meas_dt grid, after every step that ends on the
+ * grid, and at t_end; a configuration with fewer rows repeats its last row.
+ * *n_rows = rows written.  Synchronises.  TGF_E_NONFINITE if any measured
+ * sum was not finite. */
+tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, int32_t max_rows,
+                    int32_t *n_rows);
+
+/* Kernel timings of the last flow run with TGF_TIMING. */
+tgf_status tgf_get_timing(tgf_ctx *c, tgf_timing *out);
+
+/* max |U U^+ - 1| and max |det U - 1| over the current links of cfg (FP64
+ * reduction): out[2].  Synchronises. */
+tgf_status tgf_unitarity(tgf_ctx *c, int32_t cfg, double *out);
+
+/* Time the candidate stage-kernel variants on the loaded links (a few stages
+ * each, links restored afterwards) and keep the fastest for this context.
+ * cache_path (may be NULL): a text file of "key variant" lines read before
+ * and appended after tuning.  Synchronises. */
+tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path);
+
+/* Select a stage-kernel variant by index (0 .. tgf_variant_count()-1), or
+ * -1 for the built-in default. */
+tgf_status tgf_set_variant(tgf_ctx *c, int32_t variant);
+int32_t tgf_get_variant(tgf_ctx *c);
+int32_t tgf_variant_count(void);
+const char *tgf_variant_name(int32_t variant);
+
+/* Plain device copy of bytes (16-byte aligned pointers) on hip_stream: the
+ * calibration kernel for HBM counters.  Enqueued only. */
+tgf_status tgf_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, void *hip_stream);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *tgf_last_error(void);
+
+/* Free host state and the cached graph; never touches caller memory. */
+void tgf_destroy(tgf_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TGF_H */

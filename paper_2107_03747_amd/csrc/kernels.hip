@@ -1,0 +1,830 @@
+// kernels.hip -- HIP kernels of the twisted Wilson flow for gfx950 (CDNA4).
+//
+// Method (arXiv 2107.03747, sec. 3.1): the Wilson action with twist factors
+// Z_{mu nu}(n) on the plaquettes of the twist site, its gradient flow
+// integrated with Luscher's third-order Runge-Kutta scheme in the low-storage
+// form
+//     X_i = B_i eps F(W_i) + A_i X_{i-1},   W_{i+1} = exp(X_i) W_i,
+//     (A, B) = (0, 1/4), (-17/9, 8/9), (-1, 3/4),
+// (identical to exp(Z0/4), exp(8/9 Z1 - 17/36 Z0), exp(3/4 Z2 - 8/9 Z1 +
+// 17/36 Z0)), force F = -P_ah(Omega) with Omega the twisted staple sum, and
+// the clover observables of eq. gmunu / eq. qlatt.
+//
+// Work decomposition: a "tile" is 64 consecutive sites of one configuration
+// (one wavefront in the site mapping).  Tiles of all configurations of a
+// batch are numbered consecutively; a wavefront finds its configuration by a
+// wave-uniform binary search in the tile prefix table, so one launch covers
+// the whole batch.  Each stage is one launch: links are read from one
+// ping-pong buffer and written to the other, so no stage reads what another
+// work-group of the same launch writes.
+#include <hip/hip_runtime.h>
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "launch.h"
+#include "layout.h"
+#include "su3_dev.h"
+
+namespace tgf {
+
+constexpr int kTile = 64;
+
+// ---------------------------------------------------------------------------
+// geometry
+
+struct Geo {
+    int d[4];
+    int s[4];      // index strides
+    int n[4];      // coordinates of this site
+    int i;         // site index
+    __device__ __forceinline__ int up(int mu) const {        // delta to n + mu
+        return n[mu] == d[mu] - 1 ? -(d[mu] - 1) * s[mu] : s[mu];
+    }
+    __device__ __forceinline__ int dn(int mu) const {        // delta to n - mu
+        return n[mu] == 0 ? (d[mu] - 1) * s[mu] : -s[mu];
+    }
+};
+
+__device__ __forceinline__ Geo make_geo(const CfgDesc &c, int i) {
+    Geo g;
+    g.i = i;
+#pragma unroll
+    for (int m = 0; m < 4; m++) g.d[m] = c.d[m];
+    g.s[0] = 1;
+    g.s[1] = c.d[0];
+    g.s[2] = c.d[0] * c.d[1];
+    g.s[3] = g.s[2] * c.d[2];
+    int r = i;
+    g.n[0] = r % c.d[0]; r /= c.d[0];
+    g.n[1] = r % c.d[1]; r /= c.d[1];
+    g.n[2] = r % c.d[2];
+    g.n[3] = r / c.d[2];
+    return g;
+}
+
+__device__ __forceinline__ int plane_index(int mu, int nu) {
+    // (0,1)->0 (0,2)->1 (0,3)->2 (1,2)->3 (1,3)->4 (2,3)->5, mu < nu
+    return mu == 0 ? nu - 1 : (mu == 1 ? nu + 1 : 5);
+}
+
+// twist exponent of Z_{mu nu} (antisymmetric mod 3)
+__device__ __forceinline__ int twist_exp(const CfgDesc &c, int mu, int nu) {
+    if (mu < nu) return c.tw[plane_index(mu, nu)];
+    int t = c.tw[plane_index(nu, mu)];
+    return t ? 3 - t : 0;
+}
+
+// omega^k, omega = exp(2 pi i / 3)
+template <class R>
+__device__ __forceinline__ cx<R> omega_pow(int k) {
+    const R h = R(0.86602540378443864676);
+    if (k == 1) return {R(-0.5), h};
+    if (k == 2) return {R(-0.5), -h};
+    return {R(1), R(0)};
+}
+
+template <class R>
+__device__ __forceinline__ void m_scale(M3<R> &A, cx<R> z) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) A.e[i][j] = cmul(z, A.e[i][j]);
+}
+
+// wave-uniform: which config (exec order) holds tile t
+__device__ __forceinline__ int find_cfg(const int *__restrict__ tile_start, int n, int t) {
+    int lo = 0, hi = n;   // tile_start[lo] <= t < tile_start[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (tile_start[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// link storage: [mu][entry][stride] complex
+
+template <class R, int NE>
+struct Links {
+    const cx<R> *__restrict__ p;
+    int stride;
+    __device__ __forceinline__ M3<R> operator()(int mu, int i) const {
+        const cx<R> *q = p + (size_t)(mu * NE) * stride + i;
+        M3<R> U;
+        U.e[0][0] = q[0];
+        U.e[0][1] = q[(size_t)stride];
+        U.e[0][2] = q[(size_t)2 * stride];
+        U.e[1][0] = q[(size_t)3 * stride];
+        U.e[1][1] = q[(size_t)4 * stride];
+        U.e[1][2] = q[(size_t)5 * stride];
+        if constexpr (NE == 9) {
+            U.e[2][0] = q[(size_t)6 * stride];
+            U.e[2][1] = q[(size_t)7 * stride];
+            U.e[2][2] = q[(size_t)8 * stride];
+        } else {
+            rebuild_row2(U);
+        }
+        return U;
+    }
+};
+
+template <class R, int NE>
+__device__ __forceinline__ void store_link(cx<R> *__restrict__ p, int stride, int mu, int i,
+                                           const M3<R> &U) {
+    cx<R> *q = p + (size_t)(mu * NE) * stride + i;
+    q[0] = U.e[0][0];
+    q[(size_t)stride] = U.e[0][1];
+    q[(size_t)2 * stride] = U.e[0][2];
+    q[(size_t)3 * stride] = U.e[1][0];
+    q[(size_t)4 * stride] = U.e[1][1];
+    q[(size_t)5 * stride] = U.e[1][2];
+    if constexpr (NE == 9) {
+        q[(size_t)6 * stride] = U.e[2][0];
+        q[(size_t)7 * stride] = U.e[2][1];
+        q[(size_t)8 * stride] = U.e[2][2];
+    }
+}
+
+// FP64 reunitarisation: normalise row 0, orthogonalise and normalise row 1,
+// row 2 = conj(row0 x row1).
+template <class R>
+__device__ __forceinline__ void reunitarise(M3<R> &U) {
+    double a[3][2], b[3][2];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        a[k][0] = (double)U.e[0][k].x; a[k][1] = (double)U.e[0][k].y;
+        b[k][0] = (double)U.e[1][k].x; b[k][1] = (double)U.e[1][k].y;
+    }
+    double na = 0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) na += a[k][0] * a[k][0] + a[k][1] * a[k][1];
+    na = 1.0 / sqrt(na);
+#pragma unroll
+    for (int k = 0; k < 3; k++) { a[k][0] *= na; a[k][1] *= na; }
+    double dr = 0, di = 0;   // conj(a) . b
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        dr += a[k][0] * b[k][0] + a[k][1] * b[k][1];
+        di += a[k][0] * b[k][1] - a[k][1] * b[k][0];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        b[k][0] -= dr * a[k][0] - di * a[k][1];
+        b[k][1] -= dr * a[k][1] + di * a[k][0];
+    }
+    double nb = 0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) nb += b[k][0] * b[k][0] + b[k][1] * b[k][1];
+    nb = 1.0 / sqrt(nb);
+#pragma unroll
+    for (int k = 0; k < 3; k++) { b[k][0] *= nb; b[k][1] *= nb; }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        // (a x b)_k = a_k1 b_k2 - a_k2 b_k1, then conjugate
+        double cr = a[k1][0] * b[k2][0] - a[k1][1] * b[k2][1] - (a[k2][0] * b[k1][0] - a[k2][1] * b[k1][1]);
+        double ci = a[k1][0] * b[k2][1] + a[k1][1] * b[k2][0] - (a[k2][0] * b[k1][1] + a[k2][1] * b[k1][0]);
+        U.e[0][k] = {(R)a[k][0], (R)a[k][1]};
+        U.e[1][k] = {(R)b[k][0], (R)b[k][1]};
+        U.e[2][k] = {(R)cr, (R)(-ci)};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// staples
+
+// Upper plaquette P_{mu nu}(n) = U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+,
+// multiplied by its twist factor Z^*_{mu nu}(n).
+template <class R, int NE>
+__device__ __forceinline__ M3<R> upper_plaq(const Links<R, NE> &W, const CfgDesc &c,
+                                            const Geo &g, int mu, int nu) {
+    M3<R> A = mul_nn(W(mu, g.i), W(nu, g.i + g.up(mu)));
+    A = mul_nd(A, W(mu, g.i + g.up(nu)));
+    A = mul_nd(A, W(nu, g.i));
+    int k = twist_exp(c, mu, nu);
+    if (k && g.n[mu] == 0 && g.n[nu] == 0) m_scale(A, cconj(omega_pow<R>(k)));
+    return A;
+}
+
+// Upper staple U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+ times Z^*_{mu nu}(n).
+template <class R, int NE>
+__device__ __forceinline__ M3<R> upper_staple(const Links<R, NE> &W, const CfgDesc &c,
+                                              const Geo &g, int mu, int nu) {
+    M3<R> A = mul_nd(W(nu, g.i + g.up(mu)), W(mu, g.i + g.up(nu)));
+    A = mul_nd(A, W(nu, g.i));
+    int k = twist_exp(c, mu, nu);
+    if (k && g.n[mu] == 0 && g.n[nu] == 0) m_scale(A, cconj(omega_pow<R>(k)));
+    return A;
+}
+
+// Lower staple U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu) times Z_{mu nu}(n-nu):
+// the plaquette P_{mu nu}(n-nu) enters the action with Z^*, and it contains
+// U_mu(n)^+, so its contribution to Omega_mu(n) is the adjoint.
+template <class R, int NE>
+__device__ __forceinline__ M3<R> lower_staple(const Links<R, NE> &W, const CfgDesc &c,
+                                              const Geo &g, int mu, int nu) {
+    int imn = g.i + g.dn(nu);
+    M3<R> T = mul_nn(W(mu, imn), W(nu, imn + g.up(mu)));
+    M3<R> L = mul_dn(T, W(nu, imn));
+    int k = twist_exp(c, mu, nu);
+    int nnu = g.n[nu] == 0 ? g.d[nu] - 1 : g.n[nu] - 1;
+    if (k && g.n[mu] == 0 && nnu == 0) m_scale(L, omega_pow<R>(k));
+    return L;
+}
+
+// RK stage tail for one link: X = B eps F + A X_old; W_out = exp(X) W_in.
+template <class R, int NE>
+__device__ __forceinline__ void update_link(const Links<R, NE> &W, cx<R> *__restrict__ Wout,
+                                            cx<R> *__restrict__ X, int stride, int mu, int i,
+                                            const M3<R> &Omega, R beps, R a, int stage,
+                                            int reunit) {
+    Alg<R> Z = proj_ah(Omega, -beps);
+    cx<R> *xp = X + (size_t)(mu * 4) * stride + i;
+    if (stage > 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            cx<R> o = xp[(size_t)k * stride];
+            Z.a[2 * k] = fma(a, o.x, Z.a[2 * k]);
+            Z.a[2 * k + 1] = fma(a, o.y, Z.a[2 * k + 1]);
+        }
+    }
+    if (stage < 2) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) xp[(size_t)k * stride] = cx<R>{Z.a[2 * k], Z.a[2 * k + 1]};
+    }
+    M3<R> E = su3_exp(Z);
+    M3<R> U = W(mu, i);
+    M3<R> N;
+    if constexpr (NE == 9) {
+        N = mul_nn(E, U);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                cx<R> s = cmul(E.e[r][0], U.e[0][j]);
+                s = cmadd(s, E.e[r][1], U.e[1][j]);
+                s = cmadd(s, E.e[r][2], U.e[2][j]);
+                N.e[r][j] = s;
+            }
+    }
+    if (reunit) reunitarise(N);
+    store_link<R, NE>(Wout, stride, mu, i, N);
+}
+
+__constant__ double kRkA[3] = {0.0, -17.0 / 9.0, -1.0};
+__constant__ double kRkB[3] = {0.25, 8.0 / 9.0, 0.75};
+
+struct StageArgs {
+    const CfgDesc *cfgs;
+    const int *tile_start;
+    int n_act;
+    int n_tiles;
+    int step;
+    int stage;
+    double eps;
+    int reunit;
+    int xcd;        // 1: remap blocks so each XCD owns a contiguous tile range
+};
+
+__device__ __forceinline__ int remap_block(int b, int nb, int xcd) {
+    if (!xcd) return b;
+    int per = (nb + 7) >> 3;             // grid is padded to 8*per blocks
+    return (b & 7) * per + (b >> 3);
+}
+
+// One thread per site: the six upper plaquettes feed both of their links
+// (P_{nu mu} = P_{mu nu}^+), the twelve lower staples are summed per link
+// before the single U_mu(n) S product.
+template <class R, int NE>
+__global__ __launch_bounds__(256) void stage_site_kernel(StageArgs a) {
+    const int nb = (a.n_tiles + 3) >> 2;
+    const int b = remap_block(blockIdx.x, nb, a.xcd);
+    if (b >= nb) return;
+    const int tile = b * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= a.n_tiles) return;
+    const int ci = find_cfg(a.tile_start, a.n_act, tile);
+    const CfgDesc c = a.cfgs[ci];
+    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
+    if (i >= c.V) return;
+
+    const int in = (c.cur + 3 * a.step + a.stage) & 1;
+    const Links<R, NE> W{(const cx<R> *)c.W[in], c.stride};
+    cx<R> *Wout = (cx<R> *)c.W[in ^ 1];
+    cx<R> *X = (cx<R> *)c.X;
+    const double eps = a.step < c.n_full ? a.eps : c.eps_last;
+    const R beps = (R)(kRkB[a.stage] * eps);
+    const R ac = (R)kRkA[a.stage];
+    const Geo g = make_geo(c, i);
+
+    M3<R> acc[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) m_zero(acc[mu]);
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++)
+#pragma unroll
+        for (int nu = mu + 1; nu < 4; nu++) {
+            M3<R> P = upper_plaq(W, c, g, mu, nu);
+            m_acc(acc[mu], P);
+            m_acc_scaled_dag(acc[nu], cx<R>{R(1), R(0)}, P);
+        }
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+        M3<R> S;
+        m_zero(S);
+#pragma unroll
+        for (int nu = 0; nu < 4; nu++) {
+            if (nu == mu) continue;
+            m_acc(S, lower_staple(W, c, g, mu, nu));
+        }
+        M3<R> US = mul_nn(W(mu, i), S);
+        m_acc(acc[mu], US);
+        update_link<R, NE>(W, Wout, X, c.stride, mu, i, acc[mu], beps, ac, a.stage, a.reunit);
+    }
+}
+
+// One thread per link: a work-group is one tile of 64 sites x 4 directions,
+// wave w handles direction mu = w for the 64 sites (mu is a compile-time
+// constant inside the body, so all coordinate arrays stay in registers).
+template <class R, int NE, int MU>
+__device__ __forceinline__ void link_body(const StageArgs &a, const CfgDesc &c, int i) {
+    const int in = (c.cur + 3 * a.step + a.stage) & 1;
+    const Links<R, NE> W{(const cx<R> *)c.W[in], c.stride};
+    cx<R> *Wout = (cx<R> *)c.W[in ^ 1];
+    cx<R> *X = (cx<R> *)c.X;
+    const double eps = a.step < c.n_full ? a.eps : c.eps_last;
+    const R beps = (R)(kRkB[a.stage] * eps);
+    const R ac = (R)kRkA[a.stage];
+    const Geo g = make_geo(c, i);
+
+    M3<R> S;
+    m_zero(S);
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == MU) continue;
+        m_acc(S, upper_staple(W, c, g, MU, nu));
+        m_acc(S, lower_staple(W, c, g, MU, nu));
+    }
+    M3<R> Om = mul_nn(W(MU, i), S);
+    update_link<R, NE>(W, Wout, X, c.stride, MU, i, Om, beps, ac, a.stage, a.reunit);
+}
+
+template <class R, int NE>
+__global__ __launch_bounds__(256) void stage_link_kernel(StageArgs a) {
+    const int b = remap_block(blockIdx.x, a.n_tiles, a.xcd);
+    if (b >= a.n_tiles) return;
+    const int tile = b;
+    const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ci = find_cfg(a.tile_start, a.n_act, tile);
+    const CfgDesc c = a.cfgs[ci];
+    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
+    if (i >= c.V) return;
+    switch (mu) {
+        case 0: link_body<R, NE, 0>(a, c, i); break;
+        case 1: link_body<R, NE, 1>(a, c, i); break;
+        case 2: link_body<R, NE, 2>(a, c, i); break;
+        default: link_body<R, NE, 3>(a, c, i); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// measurement: clover G (eq. gmunu), e(n), q(n), plaquette, action
+
+template <class R>
+struct Herm {   // Hermitian 3x3: diag reals + upper off-diagonals
+    R d[3];
+    cx<R> o[3];   // 01, 02, 12
+};
+
+template <class R>
+__device__ __forceinline__ R tr_herm2(const Herm<R> &a, const Herm<R> &b) {
+    R s = a.d[0] * b.d[0] + a.d[1] * b.d[1] + a.d[2] * b.d[2];
+    R o = 0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) o += a.o[k].x * b.o[k].x + a.o[k].y * b.o[k].y;
+    return s + R(2) * o;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <class R, int NE>
+__device__ __forceinline__ Herm<R> clover_G(const Links<R, NE> &W, const CfgDesc &c, const Geo &g,
+                                            int mu, int nu, R &retr_plaq) {
+    const int i = g.i;
+    const int i_m = i + g.dn(mu), i_n = i + g.dn(nu);
+    const int i_mn = i_m + g.dn(nu);
+    const int k = twist_exp(c, mu, nu);
+    const int nm = g.n[mu] == 0 ? g.d[mu] - 1 : g.n[mu] - 1;
+    const int nn = g.n[nu] == 0 ? g.d[nu] - 1 : g.n[nu] - 1;
+    const cx<R> zs = cconj(omega_pow<R>(k));
+    M3<R> C, L;
+    // leaf 1: Z^*(n) U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
+    L = mul_nn(W(mu, i), W(nu, i + g.up(mu)));
+    L = mul_nd(L, W(mu, i + g.up(nu)));
+    L = mul_nd(L, W(nu, i));
+    if (k && g.n[mu] == 0 && g.n[nu] == 0) m_scale(L, zs);
+    retr_plaq = L.e[0][0].x + L.e[1][1].x + L.e[2][2].x;
+    C = L;
+    // leaf 2: Z^*(n-nu) U_nu(n-nu)^+ U_mu(n-nu) U_nu(n-nu+mu) U_mu(n)^+
+    L = mul_dn(W(nu, i_n), W(mu, i_n));
+    L = mul_nn(L, W(nu, i_n + g.up(mu)));
+    L = mul_nd(L, W(mu, i));
+    if (k && g.n[mu] == 0 && nn == 0) m_scale(L, zs);
+    m_acc(C, L);
+    // leaf 3: Z^*(n-mu) U_nu(n) U_mu(n-mu+nu)^+ U_nu(n-mu)^+ U_mu(n-mu)
+    L = mul_nd(W(nu, i), W(mu, i_m + g.up(nu)));
+    L = mul_nd(L, W(nu, i_m));
+    L = mul_nn(L, W(mu, i_m));
+    if (k && nm == 0 && g.n[nu] == 0) m_scale(L, zs);
+    m_acc(C, L);
+    // leaf 4: Z^*(n-mu-nu) U_mu(n-mu)^+ U_nu(n-mu-nu)^+ U_mu(n-mu-nu) U_nu(n-nu)
+    {
+        M3<R> A = mul_nn(W(nu, i_mn), W(mu, i_m));   // (U_mu(n-mu)^+ U_nu(n-mu-nu)^+)^+
+        L = mul_dn(A, W(mu, i_mn));
+        L = mul_nn(L, W(nu, i_n));
+    }
+    if (k && nm == 0 && nn == 0) m_scale(L, zs);
+    m_acc(C, L);
+    // G = -(i/8)(C - C^+)
+    Herm<R> G;
+    const R q = R(0.125);
+#pragma unroll
+    for (int a = 0; a < 3; a++) G.d[a] = R(2) * q * C.e[a][a].y;
+    const int ia[3] = {0, 0, 1}, ib[3] = {1, 2, 2};
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+        cx<R> u = C.e[ia[t]][ib[t]], v = C.e[ib[t]][ia[t]];
+        // C_ab - conj(C_ba), times -i/8
+        R dr = u.x - v.x, di = u.y + v.y;
+        G.o[t] = {q * di, -q * dr};
+    }
+    return G;
+}
+
+template <class R, int NE>
+__global__ __launch_bounds__(256) void measure_kernel(const CfgDesc *__restrict__ cfgs,
+                                                      const int *__restrict__ tile_start, int n_cfg,
+                                                      int n_tiles, const MeasSlot *__restrict__ slots,
+                                                      double *__restrict__ partials, int buf_sel) {
+    const int tile = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= n_tiles) return;
+    const int ci = find_cfg(tile_start, n_cfg, tile);
+    if (slots[ci].row < 0) return;
+    const CfgDesc c = cfgs[ci];
+    const int i = (tile - tile_start[ci]) * kTile + (threadIdx.x & 63);
+    double e = 0, q = 0, p = 0, s = 0;
+    if (i < c.V) {
+        const int sel = buf_sel < 0 ? c.cur : ((c.cur + buf_sel) & 1);
+        const Links<R, NE> W{(const cx<R> *)c.W[sel], c.stride};
+        const Geo g = make_geo(c, i);
+        // planes in dual pairs: (01,23), (02,13), (03,12); q picks up
+        // Tr G01 G23 - Tr G02 G13 + Tr G03 G12
+        R er = 0, pr = 0, sr = 0, qr = 0;
+        const int pa[3][2] = {{0, 1}, {0, 2}, {0, 3}}, pb[3][2] = {{2, 3}, {1, 3}, {1, 2}};
+#pragma unroll
+        for (int t = 0; t < 3; t++) {
+            R p1, p2;
+            Herm<R> Ga = clover_G(W, c, g, pa[t][0], pa[t][1], p1);
+            Herm<R> Gb = clover_G(W, c, g, pb[t][0], pb[t][1], p2);
+            er += tr_herm2(Ga, Ga) + tr_herm2(Gb, Gb);
+            pr += p1 + p2;
+            sr += (R(3) - p1) + (R(3) - p2);
+            R x = tr_herm2(Ga, Gb);
+            qr += (t == 1) ? -x : x;
+        }
+        e = (double)er;
+        q = (double)qr * (1.0 / (4.0 * M_PI * M_PI));
+        p = (double)pr;
+        s = (double)sr;
+    }
+    e = wave_sum(e);
+    q = wave_sum(q);
+    p = wave_sum(p);
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) {
+        double *o = partials + (size_t)tile * 4;
+        o[0] = e; o[1] = q; o[2] = p; o[3] = s;
+    }
+}
+
+// One work-group per configuration: fixed-order sum of its tile partials.
+__global__ __launch_bounds__(256) void finalize_kernel(const CfgDesc *__restrict__ cfgs,
+                                                       const int *__restrict__ tile_start,
+                                                       const MeasSlot *__restrict__ slots,
+                                                       const double *__restrict__ partials,
+                                                       double *__restrict__ rows, int n_cfg_total,
+                                                       int *__restrict__ flag) {
+    const int ci = blockIdx.x;
+    const MeasSlot sl = slots[ci];
+    if (sl.row < 0) return;
+    const CfgDesc &c = cfgs[ci];
+    const int t0 = tile_start[ci], t1 = tile_start[ci + 1];
+    double acc[4] = {0, 0, 0, 0};
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc[k] += partials[(size_t)t * 4 + k];
+    }
+    __shared__ double red[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) acc[k] = wave_sum(acc[k]);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 4; k++) red[w][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) tot[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+        const double V = (double)c.V;
+        const double E = tot[0] / V;
+        double *r = rows + ((size_t)sl.row * n_cfg_total + c.user) * 6;
+        r[0] = sl.t;
+        r[1] = E;
+        r[2] = sl.t * sl.t * E;
+        r[3] = tot[2] / (18.0 * V);
+        r[4] = tot[1];
+        r[5] = tot[3];
+        if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2]) || !isfinite(tot[3]))
+            *flag = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ingest / export / checks
+
+template <class R, int NE>
+__global__ __launch_bounds__(256) void pack_kernel(const double2 *__restrict__ src,
+                                                   cx<R> *__restrict__ W, int V, int stride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mu = blockIdx.y;
+    if (i >= V) return;
+    const double2 *s = src + ((size_t)i * 4 + mu) * 9;
+    cx<R> *q = W + (size_t)(mu * NE) * stride + i;
+#pragma unroll
+    for (int e = 0; e < NE; e++) {
+        double2 v = s[e];
+        q[(size_t)e * stride] = cx<R>{(R)v.x, (R)v.y};
+    }
+}
+
+template <class R, int NE>
+__global__ __launch_bounds__(256) void unpack_kernel(const cx<R> *__restrict__ W,
+                                                     double2 *__restrict__ dst, int V, int stride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mu = blockIdx.y;
+    if (i >= V) return;
+    const cx<R> *q = W + (size_t)(mu * NE) * stride + i;
+    M3<double> U;
+#pragma unroll
+    for (int e = 0; e < NE; e++) {
+        cx<R> v = q[(size_t)e * stride];
+        U.e[e / 3][e % 3] = {(double)v.x, (double)v.y};
+    }
+    if constexpr (NE == 6) rebuild_row2(U);
+    double2 *d = dst + ((size_t)i * 4 + mu) * 9;
+#pragma unroll
+    for (int e = 0; e < 9; e++) d[e] = make_double2(U.e[e / 3][e % 3].x, U.e[e / 3][e % 3].y);
+}
+
+__device__ __forceinline__ double finite_or_inf(double v) { return (v <= DBL_MAX) ? v : INFINITY; }
+
+__device__ __forceinline__ void su3_defects(const M3<double> &U, double &du, double &dd) {
+    double m = 0;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            double re = (i == j) ? -1.0 : 0.0, im = 0;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                re += U.e[i][k].x * U.e[j][k].x + U.e[i][k].y * U.e[j][k].y;
+                im += U.e[i][k].y * U.e[j][k].x - U.e[i][k].x * U.e[j][k].y;
+            }
+            m = fmax(m, finite_or_inf(sqrt(re * re + im * im)));
+        }
+    cx<double> c0 = csub(cmul(U.e[1][1], U.e[2][2]), cmul(U.e[1][2], U.e[2][1]));
+    cx<double> c1 = csub(cmul(U.e[1][2], U.e[2][0]), cmul(U.e[1][0], U.e[2][2]));
+    cx<double> c2 = csub(cmul(U.e[1][0], U.e[2][1]), cmul(U.e[1][1], U.e[2][0]));
+    cx<double> det = cmul(U.e[0][0], c0);
+    det = cmadd(det, U.e[0][1], c1);
+    det = cmadd(det, U.e[0][2], c2);
+    du = m;
+    dd = finite_or_inf(sqrt((det.x - 1) * (det.x - 1) + det.y * det.y));
+}
+
+template <class R, int NE, bool CANON>
+__global__ __launch_bounds__(256) void check_kernel(const void *__restrict__ src, int V, int stride,
+                                                    double *__restrict__ partials) {
+    const int tile = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i = tile * kTile + (threadIdx.x & 63);
+    double du = 0, dd = 0;
+    if (i < V) {
+        for (int mu = 0; mu < 4; mu++) {
+            M3<double> U;
+            if constexpr (CANON) {
+                const double2 *s = (const double2 *)src + ((size_t)i * 4 + mu) * 9;
+#pragma unroll
+                for (int e = 0; e < 9; e++) U.e[e / 3][e % 3] = {s[e].x, s[e].y};
+            } else {
+                const cx<R> *q = (const cx<R> *)src + (size_t)(mu * NE) * stride + i;
+#pragma unroll
+                for (int e = 0; e < NE; e++) {
+                    cx<R> v = q[(size_t)e * stride];
+                    U.e[e / 3][e % 3] = {(double)v.x, (double)v.y};
+                }
+                if constexpr (NE == 6) rebuild_row2(U);
+            }
+            double a, b;
+            su3_defects(U, a, b);
+            du = fmax(du, a);
+            dd = fmax(dd, b);
+        }
+    }
+    du = wave_max(du);
+    dd = wave_max(dd);
+    const int ntiles = (V + kTile - 1) / kTile;
+    if ((threadIdx.x & 63) == 0 && tile < ntiles) {
+        partials[(size_t)tile * 2] = du;
+        partials[(size_t)tile * 2 + 1] = dd;
+    }
+}
+
+__global__ __launch_bounds__(256) void check_final_kernel(const double *__restrict__ partials,
+                                                          int ntiles, double *__restrict__ out) {
+    double a = 0, b = 0;
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        a = fmax(a, partials[(size_t)t * 2]);
+        b = fmax(b, partials[(size_t)t * 2 + 1]);
+    }
+    a = wave_max(a);
+    b = wave_max(b);
+    __shared__ double red[4][2];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[w][0] = a; red[w][1] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = fmax(fmax(red[0][0], red[1][0]), fmax(red[2][0], red[3][0]));
+        out[1] = fmax(fmax(red[0][1], red[1][1]), fmax(red[2][1], red[3][1]));
+    }
+}
+
+__global__ void fill_int_kernel(int *dst, int n, int value) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = value;
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const float4 *__restrict__ src,
+                                                   float4 *__restrict__ dst, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t step = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += step) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+const char *variant_name(int v) {
+    switch (v) {
+        case V_SITE: return "site";
+        case V_LINK: return "link";
+        case V_SITE_XCD: return "site_xcd";
+        case V_LINK_XCD: return "link_xcd";
+        default: return "?";
+    }
+}
+
+template <class R, int NE>
+static hipError_t launch_stage_t(int variant, hipStream_t s, const StageArgs &a) {
+    const bool xcd = variant == V_SITE_XCD || variant == V_LINK_XCD;
+    StageArgs b = a;
+    b.xcd = xcd ? 1 : 0;
+    if (variant == V_SITE || variant == V_SITE_XCD) {
+        int nb = (a.n_tiles + 3) / 4;
+        if (xcd) nb = ((nb + 7) / 8) * 8;
+        hipLaunchKernelGGL((stage_site_kernel<R, NE>), dim3(nb), dim3(256), 0, s, b);
+    } else {
+        int nb = a.n_tiles;
+        if (xcd) nb = ((nb + 7) / 8) * 8;
+        hipLaunchKernelGGL((stage_link_kernel<R, NE>), dim3(nb), dim3(256), 0, s, b);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(int variant, Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
+                        const int *tile_start, int n_act, int n_tiles, int step, int stage,
+                        double eps, int reunit) {
+    if (n_tiles <= 0) return hipSuccess;
+    StageArgs a{cfgs, tile_start, n_act, n_tiles, step, stage, eps, reunit, 0};
+    if (p == P_F64) return launch_stage_t<double, 9>(variant, s, a);
+    if (c12) return launch_stage_t<float, 6>(variant, s, a);
+    return launch_stage_t<float, 9>(variant, s, a);
+}
+
+hipError_t launch_measure(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
+                          const int *tile_start, int n_cfg, int n_tiles, const MeasSlot *slots,
+                          double *partials, int buf_sel) {
+    if (n_tiles <= 0) return hipSuccess;
+    dim3 grid((n_tiles + 3) / 4);
+    if (p == P_F64)
+        hipLaunchKernelGGL((measure_kernel<double, 9>), grid, dim3(256), 0, s, cfgs, tile_start,
+                           n_cfg, n_tiles, slots, partials, buf_sel);
+    else if (c12)
+        hipLaunchKernelGGL((measure_kernel<float, 6>), grid, dim3(256), 0, s, cfgs, tile_start,
+                           n_cfg, n_tiles, slots, partials, buf_sel);
+    else
+        hipLaunchKernelGGL((measure_kernel<float, 9>), grid, dim3(256), 0, s, cfgs, tile_start,
+                           n_cfg, n_tiles, slots, partials, buf_sel);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(hipStream_t s, const CfgDesc *cfgs, const int *tile_start, int n_cfg,
+                           const MeasSlot *slots, const double *partials, double *rows,
+                           int n_cfg_total, int *flag) {
+    if (n_cfg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_cfg), dim3(256), 0, s, cfgs, tile_start, slots,
+                       partials, rows, n_cfg_total, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(Prec p, bool c12, hipStream_t s, const void *src, void *W, int V,
+                       int stride) {
+    dim3 grid((V + 255) / 256, 4);
+    const double2 *in = (const double2 *)src;
+    if (p == P_F64)
+        hipLaunchKernelGGL((pack_kernel<double, 9>), grid, dim3(256), 0, s, in,
+                           (cx<double> *)W, V, stride);
+    else if (c12)
+        hipLaunchKernelGGL((pack_kernel<float, 6>), grid, dim3(256), 0, s, in, (cx<float> *)W,
+                           V, stride);
+    else
+        hipLaunchKernelGGL((pack_kernel<float, 9>), grid, dim3(256), 0, s, in, (cx<float> *)W,
+                           V, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(Prec p, bool c12, hipStream_t s, const void *W, void *dst, int V,
+                         int stride) {
+    dim3 grid((V + 255) / 256, 4);
+    double2 *out = (double2 *)dst;
+    if (p == P_F64)
+        hipLaunchKernelGGL((unpack_kernel<double, 9>), grid, dim3(256), 0, s,
+                           (const cx<double> *)W, out, V, stride);
+    else if (c12)
+        hipLaunchKernelGGL((unpack_kernel<float, 6>), grid, dim3(256), 0, s,
+                           (const cx<float> *)W, out, V, stride);
+    else
+        hipLaunchKernelGGL((unpack_kernel<float, 9>), grid, dim3(256), 0, s,
+                           (const cx<float> *)W, out, V, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void *src, int V,
+                        int stride, double *partials, double *out) {
+    const int ntiles = (V + kTile - 1) / kTile;
+    dim3 grid((ntiles + 3) / 4);
+    if (canon)
+        hipLaunchKernelGGL((check_kernel<double, 9, true>), grid, dim3(256), 0, s, src, V, stride,
+                           partials);
+    else if (p == P_F64)
+        hipLaunchKernelGGL((check_kernel<double, 9, false>), grid, dim3(256), 0, s, src, V,
+                           stride, partials);
+    else if (c12)
+        hipLaunchKernelGGL((check_kernel<float, 6, false>), grid, dim3(256), 0, s, src, V,
+                           stride, partials);
+    else
+        hipLaunchKernelGGL((check_kernel<float, 9, false>), grid, dim3(256), 0, s, src, V,
+                           stride, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(check_final_kernel, dim3(1), dim3(256), 0, s, partials, ntiles, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(hipStream_t s, int *dst, int n, int value) {
+    hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dst, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(hipStream_t s, void *dst, const void *src, size_t bytes) {
+    size_t n = bytes / 16;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const float4 *)src,
+                       (float4 *)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace tgf

@@ -1,0 +1,51 @@
+// launch.h -- host-side launchers of the device kernels (internal to libtgf).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "layout.h"
+
+namespace tgf {
+
+enum Prec { P_F64 = 0, P_F32 = 1 };
+
+// Stage-kernel variants (thread <-> link mapping and launch shape).
+enum Variant {
+    V_SITE = 0,       // one thread per site, 4 links, shared upper plaquettes
+    V_LINK = 1,       // one thread per link (wave-uniform mu), no sharing
+    V_SITE_XCD = 2,   // V_SITE with XCD-contiguous tile order
+    V_LINK_XCD = 3,   // V_LINK with XCD-contiguous tile order
+    V_COUNT = 4
+};
+const char *variant_name(int v);
+
+// All launchers enqueue on `s` and return the hipError_t of the launch.
+// `tile_start` has n_act+1 entries (exec order); tiles are 64 sites.
+hipError_t launch_stage(int variant, Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
+                        const int *tile_start, int n_act, int n_tiles, int step, int stage,
+                        double eps, int reunit);
+
+hipError_t launch_measure(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
+                          const int *tile_start, int n_cfg, int n_tiles, const MeasSlot *slots,
+                          double *partials, int buf_sel);
+
+hipError_t launch_finalize(hipStream_t s, const CfgDesc *cfgs, const int *tile_start, int n_cfg,
+                           const MeasSlot *slots, const double *partials, double *rows,
+                           int n_cfg_total, int *flag);
+
+// canonical complex128 [V][4][3][3] <-> storage buffer W (of config c)
+hipError_t launch_pack(Prec p, bool c12, hipStream_t s, const void *src, void *W, int V,
+                       int stride);
+hipError_t launch_unpack(Prec p, bool c12, hipStream_t s, const void *W, void *dst, int V,
+                         int stride);
+
+// Unitarity defects: max|UU^+ - 1|, max|det U - 1|.  Source is canonical
+// (canon = true) or storage.  Partials need ceil(V/64)*2 doubles; out 2 doubles.
+hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void *src, int V,
+                        int stride, double *partials, double *out);
+
+hipError_t launch_fill_int(hipStream_t s, int *dst, int n, int value);
+hipError_t launch_copy(hipStream_t s, void *dst, const void *src, size_t bytes);
+
+}  // namespace tgf

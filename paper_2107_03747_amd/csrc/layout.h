@@ -1,0 +1,47 @@
+// layout.h -- device-side layout of a flow context (host and device code).
+//
+// Every configuration c owns, inside the caller's workspace:
+//   W[0], W[1]  ping-pong link buffers, structure of arrays
+//               [mu (4)][entry (NE)][site (stride)] of complex R, where NE = 9
+//               (full storage, row-major entries) or 6 (rows 0 and 1 only);
+//   X           RK accumulator [mu (4)][slot (4)][site (stride)] of complex R:
+//               slots 0..2 = X01, X02, X12, slot 3 = (Im X00, Im X11).
+// `stride` is the site count rounded up to a multiple of 256 so that every
+// entry plane starts 256-byte aligned and a wavefront's 64 consecutive sites
+// read 64 consecutive complex numbers (fully coalesced).
+//
+// Shared regions: the descriptor table, the per-block reduction partials
+// (4 doubles per block: e, q, plaq, action), the FP64 observable rows, the
+// flow schedule and a status word.
+#pragma once
+
+#include <stdint.h>
+
+namespace tgf {
+
+constexpr int kBlock = 256;          // threads per work-group for site kernels
+constexpr int kMaxRows = 4096;       // rows per flow call (TGF_MAX_ROWS)
+
+struct CfgDesc {
+    int32_t d[4];         // extents
+    int32_t V;            // sites
+    int32_t stride;       // site stride of an entry plane
+    int32_t tw[6];        // twist n01 n02 n03 n12 n13 n23 (0..2)
+    int32_t user;         // index of this config in the caller's order
+    int32_t cur;          // which W buffer holds the links at step 0 of this flow
+    int32_t n_full;       // full steps of size eps this flow
+    int32_t n_steps;      // n_full + (short final step ? 1 : 0)
+    double eps_last;      // size of the short final step (0 if none)
+    double t0;            // flow time at the start of this flow
+    void *W[2];
+    void *X;
+};
+
+// Per-measurement-event schedule entry for one config (exec order).
+struct MeasSlot {
+    int32_t row;          // output row, or -1 when this config is not measured
+    int32_t pad;
+    double t;             // flow time of the measurement
+};
+
+}  // namespace tgf

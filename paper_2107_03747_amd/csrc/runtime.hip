@@ -1,0 +1,818 @@
+// runtime.hip -- host runtime of libtgf.so: the C ABI declared in tgf.h.
+//
+// Responsibilities: argument validation (before anything is enqueued),
+// carving the caller's workspace into per-configuration buffers, the flow
+// schedule (full steps of eps, one shortened last step, measurement rows),
+// ordering a batch so that the configurations still flowing at any step form
+// a prefix of the tile table (one launch per RK stage for the whole batch),
+// capturing the launch sequence of a flow into a HIP graph that is reused
+// while the sequence is unchanged, kernel timing with HIP events, and the
+// stage-variant autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/tgf.h"
+#include "launch.h"
+#include "layout.h"
+
+using namespace tgf;
+
+namespace {
+
+thread_local std::string g_err;
+
+tgf_status fail(tgf_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(TGF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct CfgHost {
+    int d[4];
+    int tw[6];
+    int V;
+    int stride;
+    int tiles;
+    size_t offW[2], offX;
+    int cur = 0;
+    double t = 0;
+    bool loaded = false;
+};
+
+struct Layout {
+    size_t off_desc, off_tiles, off_flag, off_check, off_partials, off_rows, off_meas, off_cfg0;
+    size_t total;
+    int total_tiles;
+    std::vector<CfgHost> cfg;
+};
+
+int ne_of(tgf_storage st) { return st == TGF_F32_C12 ? 6 : 9; }
+size_t cx_bytes(tgf_storage st) { return st == TGF_F64_FULL ? 16 : 8; }
+
+tgf_status validate_geoms(int32_t n_cfg, const tgf_geom *g) {
+    if (n_cfg <= 0) return fail(TGF_E_INVAL, "n_cfg must be positive");
+    if (!g) return fail(TGF_E_INVAL, "geoms is NULL");
+    for (int c = 0; c < n_cfg; c++) {
+        long long V = 1;
+        for (int m = 0; m < 4; m++) {
+            if (g[c].dims[m] < 2)
+                return fail(TGF_E_INVAL, "config " + std::to_string(c) + ": dims must be >= 2");
+            V *= g[c].dims[m];
+        }
+        if (V > (1LL << 30))
+            return fail(TGF_E_INVAL, "config " + std::to_string(c) + ": lattice too large");
+        for (int k = 0; k < 6; k++)
+            if (g[c].twist[k] < 0 || g[c].twist[k] > 2)
+                return fail(TGF_E_INVAL,
+                            "config " + std::to_string(c) + ": twist entries must be 0, 1 or 2");
+    }
+    return TGF_OK;
+}
+
+Layout make_layout(int32_t n_cfg, const tgf_geom *g, tgf_storage st) {
+    Layout L;
+    L.cfg.resize(n_cfg);
+    int tiles = 0;
+    for (int c = 0; c < n_cfg; c++) {
+        CfgHost &h = L.cfg[c];
+        h.V = 1;
+        for (int m = 0; m < 4; m++) { h.d[m] = g[c].dims[m]; h.V *= h.d[m]; }
+        for (int k = 0; k < 6; k++) h.tw[k] = g[c].twist[k];
+        h.stride = (int)align_up((size_t)h.V, 256);
+        h.tiles = (h.V + 63) / 64;
+        tiles += h.tiles;
+    }
+    L.total_tiles = tiles;
+    size_t o = 0;
+    L.off_desc = o;     o = align_up(o + sizeof(CfgDesc) * n_cfg, 256);
+    L.off_tiles = o;    o = align_up(o + sizeof(int) * (n_cfg + 1), 256);
+    L.off_flag = o;     o = align_up(o + 64, 256);
+    L.off_check = o;    o = align_up(o + 64, 256);
+    size_t partial_doubles = std::max<size_t>((size_t)tiles * 4, 2 * (size_t)tiles);
+    L.off_partials = o; o = align_up(o + sizeof(double) * partial_doubles, 256);
+    L.off_rows = o;     o = align_up(o + sizeof(double) * 6 * (size_t)kMaxRows * n_cfg, 256);
+    L.off_meas = o;     o = align_up(o + sizeof(MeasSlot) * (size_t)(kMaxRows + 1) * n_cfg, 256);
+    L.off_cfg0 = o;
+    const size_t e = cx_bytes(st);
+    const int NE = ne_of(st);
+    for (int c = 0; c < n_cfg; c++) {
+        CfgHost &h = L.cfg[c];
+        size_t wb = e * 4 * NE * (size_t)h.stride;
+        size_t xb = e * 4 * 4 * (size_t)h.stride;
+        h.offW[0] = o; o = align_up(o + wb, 256);
+        h.offW[1] = o; o = align_up(o + wb, 256);
+        h.offX = o;    o = align_up(o + xb, 256);
+    }
+    L.total = o;
+    return L;
+}
+
+struct Launch {
+    int kind;      // 0 stage, 1 measure, 2 finalize, 3 zero flag
+    int grid;      // tiles (stage/measure) or configs (finalize)
+    int n_act;
+    int step, stage;
+    int reunit;
+    int event;     // measurement event index (slot table row)
+    bool operator==(const Launch &o) const {
+        return kind == o.kind && grid == o.grid && n_act == o.n_act && step == o.step &&
+               stage == o.stage && reunit == o.reunit && event == o.event;
+    }
+};
+
+}  // namespace
+
+struct tgf_ctx {
+    int n_cfg;
+    tgf_storage st;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    Layout L;
+    int variant = -1;
+    // host pinned staging
+    char *h_stage = nullptr;
+    size_t h_stage_bytes = 0;
+    // cached graph of the last flow
+    hipGraphExec_t gexec = nullptr;
+    std::vector<Launch> glaunches;
+    double geps = 0;
+    int gvariant = -2;
+    tgf_timing timing{};
+    std::vector<hipEvent_t> events;
+
+    CfgDesc *d_desc() { return (CfgDesc *)(ws + L.off_desc); }
+    int *d_tiles() { return (int *)(ws + L.off_tiles); }
+    int *d_flag() { return (int *)(ws + L.off_flag); }
+    double *d_check() { return (double *)(ws + L.off_check); }
+    double *d_partials() { return (double *)(ws + L.off_partials); }
+    double *d_rows() { return (double *)(ws + L.off_rows); }
+    MeasSlot *d_meas() { return (MeasSlot *)(ws + L.off_meas); }
+    Prec prec() const { return st == TGF_F64_FULL ? P_F64 : P_F32; }
+    bool c12() const { return st == TGF_F32_C12; }
+    int effective_variant() const {
+        if (variant >= 0) return variant;
+        return st == TGF_F64_FULL ? V_LINK : V_SITE;
+    }
+};
+
+namespace {
+
+tgf_status ensure_stage(tgf_ctx *c, size_t bytes) {
+    if (c->h_stage_bytes >= bytes) return TGF_OK;
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    c->h_stage = nullptr;
+    c->h_stage_bytes = 0;
+    size_t nb = std::max<size_t>(bytes, 1 << 16);
+    HIP_TRY(hipHostMalloc((void **)&c->h_stage, nb, hipHostMallocDefault));
+    c->h_stage_bytes = nb;
+    return TGF_OK;
+}
+
+void fill_desc(const tgf_ctx *c, const CfgHost &h, int user, CfgDesc &d) {
+    memset(&d, 0, sizeof d);
+    for (int m = 0; m < 4; m++) d.d[m] = h.d[m];
+    d.V = h.V;
+    d.stride = h.stride;
+    for (int k = 0; k < 6; k++) d.tw[k] = h.tw[k];
+    d.user = user;
+    d.cur = h.cur;
+    d.t0 = h.t;
+    d.W[0] = c->ws + h.offW[0];
+    d.W[1] = c->ws + h.offW[1];
+    d.X = c->ws + h.offX;
+}
+
+bool on_grid(double t, double dt) {
+    if (dt <= 0) return false;
+    double k = std::floor(t / dt + 0.5);
+    return std::fabs(t - k * dt) <= 1e-9;
+}
+
+// Step plan of one configuration (same rule as the paper-independent
+// schedule stated in tgf.h): t_k = t0 + k*eps while t_k <= t_end + 1e-12,
+// then one short step to t_end if more than 1e-12 remains.
+struct Plan {
+    int n_full;
+    int n_steps;
+    double eps_last;
+    std::vector<std::pair<int, double>> meas;   // (steps done before the row, t)
+};
+
+Plan make_plan(double t0, double t_end, double eps, double dt) {
+    Plan p;
+    long n = 0;
+    while (t0 + (n + 1) * eps <= t_end + 1e-12) n++;
+    p.n_full = (int)n;
+    double t_last = t0 + n * eps;
+    bool has_short = (t_end - t_last) > 1e-12;
+    p.eps_last = has_short ? t_end - t_last : 0.0;
+    p.n_steps = p.n_full + (has_short ? 1 : 0);
+    if (on_grid(t0, dt) || p.n_steps == 0) p.meas.push_back({0, t0});
+    for (int k = 1; k <= p.n_full; k++) {
+        double t = t0 + k * eps;
+        bool last = (k == p.n_full) && !has_short;
+        if (on_grid(t, dt) || last) p.meas.push_back({k, t});
+    }
+    if (has_short) p.meas.push_back({p.n_steps, t_end});
+    return p;
+}
+
+tgf_status run_launches(tgf_ctx *c, const std::vector<Launch> &ls, double eps, bool graph,
+                        bool timing) {
+    const int variant = c->effective_variant();
+    hipStream_t s = c->stream;
+    auto issue = [&](const Launch &l) -> hipError_t {
+        switch (l.kind) {
+            case 0:
+                return launch_stage(variant, c->prec(), c->c12(), s, c->d_desc(), c->d_tiles(),
+                                    l.n_act, l.grid, l.step, l.stage, eps, l.reunit);
+            case 1:
+                return launch_measure(c->prec(), c->c12(), s, c->d_desc(), c->d_tiles(), l.n_act,
+                                      l.grid, c->d_meas() + (size_t)l.event * c->n_cfg,
+                                      c->d_partials(), l.step);
+            case 2:
+                return launch_finalize(s, c->d_desc(), c->d_tiles(), l.n_act,
+                                       c->d_meas() + (size_t)l.event * c->n_cfg, c->d_partials(),
+                                       c->d_rows(), c->n_cfg, c->d_flag());
+            default:
+                return launch_fill_int(s, c->d_flag(), 1, 0);
+        }
+    };
+    if (timing) {
+        size_t need = 2 * ls.size();
+        while (c->events.size() < need) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            c->events.push_back(e);
+        }
+        for (size_t k = 0; k < ls.size(); k++) {
+            HIP_TRY(hipEventRecord(c->events[2 * k], s));
+            HIP_TRY(issue(ls[k]));
+            HIP_TRY(hipEventRecord(c->events[2 * k + 1], s));
+        }
+        return TGF_OK;
+    }
+    if (!graph) {
+        for (const Launch &l : ls) HIP_TRY(issue(l));
+        return TGF_OK;
+    }
+    bool reuse = c->gexec && c->glaunches == ls && c->geps == eps && c->gvariant == variant;
+    if (!reuse) {
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        for (const Launch &l : ls) {
+            err = issue(l);
+            if (err != hipSuccess) break;
+        }
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (err != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(TGF_E_HIP, std::string("kernel launch during capture: ") +
+                                       hipGetErrorString(err));
+        }
+        HIP_TRY(e2);
+        hipError_t e3 = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIP_TRY(e3);
+        c->glaunches = ls;
+        c->geps = eps;
+        c->gvariant = variant;
+    }
+    HIP_TRY(hipGraphLaunch(c->gexec, s));
+    return TGF_OK;
+}
+
+tgf_status check_ctx(tgf_ctx *c) {
+    if (!c) return fail(TGF_E_INVAL, "context is NULL");
+    return TGF_OK;
+}
+
+tgf_status check_cfg(tgf_ctx *c, int32_t cfg) {
+    if (cfg < 0 || cfg >= c->n_cfg)
+        return fail(TGF_E_INVAL, "cfg index " + std::to_string(cfg) + " out of range");
+    return TGF_OK;
+}
+
+// Unitarity defects of canonical (canon) or stored links of config cfg.
+tgf_status run_check(tgf_ctx *c, int cfg, const void *src, bool canon, double out[2]) {
+    const CfgHost &h = c->L.cfg[cfg];
+    HIP_TRY(launch_check(c->prec(), c->c12(), canon, c->stream, src, h.V, h.stride,
+                         c->d_partials(), c->d_check()));
+    tgf_status st = ensure_stage(c, 64);
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(c->h_stage, c->d_check(), 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    memcpy(out, c->h_stage, 2 * sizeof(double));
+    return TGF_OK;
+}
+
+// Upload descriptors + tile prefix of the given exec order.
+tgf_status upload_tables(tgf_ctx *c, const std::vector<int> &order, const std::vector<Plan> *plans,
+                         std::vector<int> &tile_start) {
+    const int n = (int)order.size();
+    tile_start.assign(n + 1, 0);
+    for (int k = 0; k < n; k++) tile_start[k + 1] = tile_start[k] + c->L.cfg[order[k]].tiles;
+    size_t bytes = sizeof(CfgDesc) * n + sizeof(int) * (n + 1);
+    tgf_status st = ensure_stage(c, bytes);
+    if (st) return st;
+    CfgDesc *dd = (CfgDesc *)c->h_stage;
+    for (int k = 0; k < n; k++) {
+        fill_desc(c, c->L.cfg[order[k]], order[k], dd[k]);
+        if (plans) {
+            const Plan &p = (*plans)[order[k]];
+            dd[k].n_full = p.n_full;
+            dd[k].n_steps = p.n_steps;
+            dd[k].eps_last = p.eps_last;
+        }
+    }
+    int *ti = (int *)(c->h_stage + sizeof(CfgDesc) * n);
+    memcpy(ti, tile_start.data(), sizeof(int) * (n + 1));
+    HIP_TRY(hipMemcpyAsync(c->d_desc(), dd, sizeof(CfgDesc) * n, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->d_tiles(), ti, sizeof(int) * (n + 1), hipMemcpyHostToDevice,
+                           c->stream));
+    // the staging buffer is reused by the caller: wait for the copies
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return TGF_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+const char *tgf_last_error(void) { return g_err.c_str(); }
+
+size_t tgf_workspace_bytes(int32_t n_cfg, const tgf_geom *geoms, tgf_storage st) {
+    if (st < TGF_F64_FULL || st > TGF_F32_C12) return 0;
+    if (validate_geoms(n_cfg, geoms) != TGF_OK) return 0;
+    return make_layout(n_cfg, geoms, st).total;
+}
+
+tgf_status tgf_create(tgf_ctx **out, int32_t n_cfg, const tgf_geom *geoms, tgf_storage st,
+                      void *workspace_dev, size_t workspace_bytes, void *hip_stream) {
+    g_err.clear();
+    if (!out) return fail(TGF_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (st < TGF_F64_FULL || st > TGF_F32_C12) return fail(TGF_E_INVAL, "unknown storage");
+    tgf_status s = validate_geoms(n_cfg, geoms);
+    if (s) return s;
+    if (!workspace_dev) return fail(TGF_E_INVAL, "workspace is NULL");
+    if (((uintptr_t)workspace_dev) % 256)
+        return fail(TGF_E_INVAL, "workspace must be 256-byte aligned");
+    Layout L = make_layout(n_cfg, geoms, st);
+    if (workspace_bytes < L.total)
+        return fail(TGF_E_SIZE, "workspace too small: need " + std::to_string(L.total) +
+                                    " bytes, got " + std::to_string(workspace_bytes));
+    tgf_ctx *c = new (std::nothrow) tgf_ctx();
+    if (!c) return fail(TGF_E_INVAL, "out of host memory");
+    c->n_cfg = n_cfg;
+    c->st = st;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char *)workspace_dev;
+    c->ws_bytes = workspace_bytes;
+    c->L = std::move(L);
+    *out = c;
+    return TGF_OK;
+}
+
+void tgf_destroy(tgf_ctx *c) {
+    if (!c) return;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    delete c;
+}
+
+static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
+                            const void *const *links, const double *t0) {
+    for (size_t k = 0; k < cfgs.size(); k++) {
+        if (!links[k]) return fail(TGF_E_INVAL, "links pointer is NULL");
+        if (!std::isfinite(t0[k]) || t0[k] < 0) return fail(TGF_E_INVAL, "t0 must be >= 0");
+    }
+    // check every input before touching storage
+    double worst[2] = {0, 0};
+    int bad = -1;
+    for (size_t k = 0; k < cfgs.size(); k++) {
+        double d[2];
+        tgf_status s = run_check(c, cfgs[k], links[k], true, d);
+        if (s) return s;
+        if (!(d[0] <= 1e-10) || !(d[1] <= 1e-10)) {
+            bad = cfgs[k];
+            worst[0] = d[0];
+            worst[1] = d[1];
+            break;
+        }
+    }
+    if (bad >= 0) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "config %d: links not in SU(3): max|UU^+-1| = %.3g, "
+                 "max|det-1| = %.3g", bad, worst[0], worst[1]);
+        return fail(TGF_E_NOT_SU3, buf);
+    }
+    for (size_t k = 0; k < cfgs.size(); k++) {
+        CfgHost &h = c->L.cfg[cfgs[k]];
+        HIP_TRY(launch_pack(c->prec(), c->c12(), c->stream, links[k], c->ws + h.offW[0], h.V,
+                            h.stride));
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < cfgs.size(); k++) {
+        CfgHost &h = c->L.cfg[cfgs[k]];
+        h.cur = 0;
+        h.t = t0[k];
+        h.loaded = true;
+    }
+    return TGF_OK;
+}
+
+tgf_status tgf_load_links(tgf_ctx *c, int32_t cfg, const void *links_dev, double t0) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if ((s = check_cfg(c, cfg))) return s;
+    std::vector<int> v{cfg};
+    const void *p[1] = {links_dev};
+    return load_impl(c, v, p, &t0);
+}
+
+tgf_status tgf_load_links_all(tgf_ctx *c, const void *const *links_dev, const double *t0) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if (!links_dev || !t0) return fail(TGF_E_INVAL, "links_dev / t0 is NULL");
+    std::vector<int> v(c->n_cfg);
+    for (int k = 0; k < c->n_cfg; k++) v[k] = k;
+    return load_impl(c, v, links_dev, t0);
+}
+
+tgf_status tgf_store_links(tgf_ctx *c, int32_t cfg, void *links_dev) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if ((s = check_cfg(c, cfg))) return s;
+    if (!links_dev) return fail(TGF_E_INVAL, "links pointer is NULL");
+    CfgHost &h = c->L.cfg[cfg];
+    if (!h.loaded) return fail(TGF_E_STATE, "config not loaded");
+    HIP_TRY(launch_unpack(c->prec(), c->c12(), c->stream, c->ws + h.offW[h.cur], links_dev, h.V,
+                          h.stride));
+    return TGF_OK;
+}
+
+tgf_status tgf_get_time(tgf_ctx *c, int32_t cfg, double *t) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if ((s = check_cfg(c, cfg))) return s;
+    if (!t) return fail(TGF_E_INVAL, "t is NULL");
+    *t = c->L.cfg[cfg].t;
+    return TGF_OK;
+}
+
+tgf_status tgf_unitarity(tgf_ctx *c, int32_t cfg, double *out) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if ((s = check_cfg(c, cfg))) return s;
+    if (!out) return fail(TGF_E_INVAL, "out is NULL");
+    CfgHost &h = c->L.cfg[cfg];
+    if (!h.loaded) return fail(TGF_E_STATE, "config not loaded");
+    return run_check(c, cfg, c->ws + h.offW[h.cur], false, out);
+}
+
+tgf_status tgf_measure(tgf_ctx *c, tgf_obs *out_host) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if (!out_host) return fail(TGF_E_INVAL, "out_host is NULL");
+    for (int k = 0; k < c->n_cfg; k++)
+        if (!c->L.cfg[k].loaded)
+            return fail(TGF_E_STATE, "config " + std::to_string(k) + " not loaded");
+    std::vector<int> order(c->n_cfg);
+    for (int k = 0; k < c->n_cfg; k++) order[k] = k;
+    std::vector<int> ts;
+    if ((s = upload_tables(c, order, nullptr, ts))) return s;
+    // one event: every config, row 0
+    if ((s = ensure_stage(c, sizeof(MeasSlot) * c->n_cfg))) return s;
+    MeasSlot *ms = (MeasSlot *)c->h_stage;
+    for (int k = 0; k < c->n_cfg; k++) ms[k] = MeasSlot{0, 0, c->L.cfg[k].t};
+    HIP_TRY(hipMemcpyAsync(c->d_meas(), ms, sizeof(MeasSlot) * c->n_cfg, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(launch_fill_int(c->stream, c->d_flag(), 1, 0));
+    HIP_TRY(launch_measure(c->prec(), c->c12(), c->stream, c->d_desc(), c->d_tiles(), c->n_cfg,
+                           ts[c->n_cfg], c->d_meas(), c->d_partials(), -1));
+    HIP_TRY(launch_finalize(c->stream, c->d_desc(), c->d_tiles(), c->n_cfg, c->d_meas(),
+                            c->d_partials(), c->d_rows(), c->n_cfg, c->d_flag()));
+    HIP_TRY(hipStreamSynchronize(c->stream));   // the slot upload used the staging buffer
+    size_t rb = sizeof(double) * 6 * c->n_cfg;
+    HIP_TRY(hipMemcpyAsync(c->h_stage, c->d_rows(), rb, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_stage + rb, c->d_flag(), sizeof(int), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    memcpy(out_host, c->h_stage, rb);
+    int flag;
+    memcpy(&flag, c->h_stage + rb, sizeof(int));
+    if (flag) return fail(TGF_E_NONFINITE, "non-finite observable");
+    return TGF_OK;
+}
+
+tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, int32_t max_rows,
+                    int32_t *n_rows) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if (!p || !p->t_end || !rows_host || !n_rows)
+        return fail(TGF_E_INVAL, "NULL argument");
+    if (!(p->eps > 0) || !std::isfinite(p->eps)) return fail(TGF_E_INVAL, "eps must be > 0");
+    if (!(p->meas_dt >= 0) || !std::isfinite(p->meas_dt))
+        return fail(TGF_E_INVAL, "meas_dt must be >= 0");
+    if (p->reunit_every < 0) return fail(TGF_E_INVAL, "reunit_every must be >= 0");
+    if (max_rows <= 0) return fail(TGF_E_SIZE, "max_rows must be positive");
+    const int n = c->n_cfg;
+    std::vector<Plan> plans(n);
+    int n_rows_max = 0;
+    for (int k = 0; k < n; k++) {
+        const CfgHost &h = c->L.cfg[k];
+        if (!h.loaded) return fail(TGF_E_STATE, "config " + std::to_string(k) + " not loaded");
+        double te = p->t_end[k];
+        if (!std::isfinite(te) || te < h.t - 1e-12)
+            return fail(TGF_E_INVAL, "t_end[" + std::to_string(k) + "] before current t");
+        if ((te - h.t) / p->eps > 1e8) return fail(TGF_E_INVAL, "too many steps");
+        plans[k] = make_plan(h.t, std::max(te, h.t), p->eps, p->meas_dt);
+        n_rows_max = std::max(n_rows_max, (int)plans[k].meas.size());
+    }
+    if (n_rows_max > max_rows)
+        return fail(TGF_E_SIZE, "rows buffer too small: need " + std::to_string(n_rows_max));
+    if (n_rows_max > kMaxRows)
+        return fail(TGF_E_SIZE, "more than TGF_MAX_ROWS measurement rows in one call");
+
+    // exec order: longest flows first, so the active configs are a prefix
+    std::vector<int> order(n);
+    for (int k = 0; k < n; k++) order[k] = k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return plans[a].n_steps > plans[b].n_steps; });
+    const int max_steps = plans[order[0]].n_steps;
+
+    // measurement events: after `k` steps (k = 0..max_steps), configs measured then
+    std::vector<std::vector<std::pair<int, MeasSlot>>> ev(max_steps + 1);
+    for (int e = 0; e < n; e++) {
+        int cfg = order[e];
+        const Plan &pl = plans[cfg];
+        for (size_t r = 0; r < pl.meas.size(); r++)
+            ev[pl.meas[r].first].push_back({e, MeasSlot{(int)r, 0, pl.meas[r].second}});
+    }
+    int n_events = 0;
+    for (auto &v : ev) n_events += v.empty() ? 0 : 1;
+    if (n_events > kMaxRows) return fail(TGF_E_SIZE, "too many measurement events");
+
+    std::vector<int> ts;
+    if ((s = upload_tables(c, order, &plans, ts))) return s;
+    // slot table
+    if ((s = ensure_stage(c, sizeof(MeasSlot) * (size_t)std::max(n_events, 1) * n))) return s;
+    MeasSlot *ms = (MeasSlot *)c->h_stage;
+    std::vector<int> event_of_step(max_steps + 1, -1);
+    {
+        int e = 0;
+        for (int k = 0; k <= max_steps; k++) {
+            if (ev[k].empty()) continue;
+            for (int j = 0; j < n; j++) ms[(size_t)e * n + j] = MeasSlot{-1, 0, 0.0};
+            for (auto &pr : ev[k]) ms[(size_t)e * n + pr.first] = pr.second;
+            event_of_step[k] = e++;
+        }
+    }
+    if (n_events)
+        HIP_TRY(hipMemcpyAsync(c->d_meas(), ms, sizeof(MeasSlot) * (size_t)n_events * n,
+                               hipMemcpyHostToDevice, c->stream));
+
+    // active prefix per step
+    std::vector<int> active(max_steps, 0);
+    for (int k = 0; k < max_steps; k++) {
+        int a = 0;
+        while (a < n && plans[order[a]].n_steps > k) a++;
+        active[k] = a;
+    }
+
+    std::vector<Launch> ls;
+    ls.push_back(Launch{3, 1, 0, 0, 0, 0, 0});
+    auto add_meas = [&](int k) {
+        int e = event_of_step[k];
+        if (e < 0) return;
+        // configs measured at this event are all still "active" up to step k, but a
+        // config whose flow ended earlier is never measured here, so n_cfg covers it
+        ls.push_back(Launch{1, ts[n], n, 3 * k, 0, 0, e});
+        ls.push_back(Launch{2, n, n, 0, 0, 0, e});
+    };
+    add_meas(0);
+    const bool fp32 = c->st != TGF_F64_FULL;
+    for (int k = 0; k < max_steps; k++) {
+        int na = active[k];
+        int reunit = (fp32 && p->reunit_every > 0 && (k + 1) % p->reunit_every == 0) ? 1 : 0;
+        for (int st = 0; st < 3; st++)
+            ls.push_back(Launch{0, ts[na], na, k, st, st == 2 ? reunit : 0, -1});
+        add_meas(k + 1);
+    }
+
+    const bool timing = (p->flags & TGF_TIMING) != 0;
+    // the legacy null stream cannot be captured: launch directly there
+    const bool graph = !(p->flags & TGF_NO_GRAPH) && !timing && c->stream != nullptr;
+    // the slot upload reads the staging buffer; make sure it is done before reuse
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if ((s = run_launches(c, ls, p->eps, graph, timing))) return s;
+
+    // rows back
+    size_t rb = sizeof(double) * 6 * (size_t)n * n_rows_max;
+    if ((s = ensure_stage(c, rb + 64))) return s;
+    HIP_TRY(hipMemcpyAsync(c->h_stage, c->d_rows(), rb, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_stage + rb, c->d_flag(), sizeof(int), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+
+    if (timing) {
+        tgf_timing tm{};
+        const double e = (double)cx_bytes(c->st);
+        const int NE = ne_of(c->st);
+        for (size_t k = 0; k < ls.size(); k++) {
+            float ms_ = 0;
+            HIP_TRY(hipEventElapsedTime(&ms_, c->events[2 * k], c->events[2 * k + 1]));
+            const Launch &l = ls[k];
+            if (l.kind == 0) {
+                tm.stage_ms += ms_;
+                tm.stage_launches++;
+                double sites = 0;
+                for (int j = 0; j < l.n_act; j++) sites += c->L.cfg[order[j]].V;
+                // links read + written, X written (stage 0), read+written (1), read (2)
+                double xfac = l.stage == 1 ? 2.0 : 1.0;
+                tm.stage_bytes += sites * (2.0 * 4 * NE * e + xfac * 4 * 4 * e);
+                tm.stage_site_updates += sites / 3.0;
+            } else if (l.kind == 1 || l.kind == 2) {
+                tm.measure_ms += ms_;
+                tm.measure_launches++;
+            }
+        }
+        c->timing = tm;
+    }
+
+    const double *src = (const double *)c->h_stage;
+    for (int r = 0; r < n_rows_max; r++)
+        for (int k = 0; k < n; k++) {
+            int rr = std::min(r, (int)plans[k].meas.size() - 1);
+            const double *v = src + ((size_t)rr * n + k) * 6;
+            tgf_obs &o = rows_host[(size_t)r * n + k];
+            o.t = v[0]; o.E = v[1]; o.t2E = v[2]; o.plaq = v[3]; o.Q = v[4]; o.action = v[5];
+        }
+    *n_rows = n_rows_max;
+    int flag;
+    memcpy(&flag, c->h_stage + rb, sizeof(int));
+    for (int k = 0; k < n; k++) {
+        CfgHost &h = c->L.cfg[k];
+        h.cur = (h.cur + 3 * plans[k].n_steps) & 1;
+        h.t = std::max(p->t_end[k], h.t);
+    }
+    if (flag) return fail(TGF_E_NONFINITE, "non-finite observable during the flow");
+    return TGF_OK;
+}
+
+tgf_status tgf_get_timing(tgf_ctx *c, tgf_timing *out) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if (!out) return fail(TGF_E_INVAL, "out is NULL");
+    *out = c->timing;
+    return TGF_OK;
+}
+
+int32_t tgf_variant_count(void) { return V_COUNT; }
+
+const char *tgf_variant_name(int32_t v) {
+    if (v < 0 || v >= V_COUNT) return "default";
+    return variant_name(v);
+}
+
+tgf_status tgf_set_variant(tgf_ctx *c, int32_t v) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if (v < -1 || v >= V_COUNT) return fail(TGF_E_INVAL, "variant out of range");
+    c->variant = v;
+    return TGF_OK;
+}
+
+int32_t tgf_get_variant(tgf_ctx *c) { return c ? c->effective_variant() : -1; }
+
+static std::string tune_key(tgf_ctx *c) {
+    std::ostringstream k;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        k << prop.gcnArchName;
+    else
+        k << "unknown";
+    k << "/st" << (int)c->st;
+    for (auto &h : c->L.cfg) k << "/" << h.d[0] << "x" << h.d[1] << "x" << h.d[2] << "x" << h.d[3];
+    std::string s = k.str();
+    for (char &ch : s)
+        if (ch == ' ') ch = '_';
+    return s;
+}
+
+tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    for (int k = 0; k < c->n_cfg; k++)
+        if (!c->L.cfg[k].loaded)
+            return fail(TGF_E_STATE, "config " + std::to_string(k) + " not loaded");
+    const std::string key = tune_key(c);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string k2;
+        int v;
+        while (in >> k2 >> v)
+            if (k2 == key && v >= 0 && v < V_COUNT) {
+                c->variant = v;
+                return TGF_OK;
+            }
+    }
+    // time stage 0 (reads the current links, writes the other buffer and X:
+    // the loaded state is not modified) for every variant
+    const int n = c->n_cfg;
+    std::vector<int> order(n);
+    for (int k = 0; k < n; k++) order[k] = k;
+    std::vector<Plan> plans(n);
+    for (int k = 0; k < n; k++) {
+        plans[k].n_full = 1;
+        plans[k].n_steps = 1;
+        plans[k].eps_last = 0;
+    }
+    std::vector<int> ts;
+    if ((s = upload_tables(c, order, &plans, ts))) return s;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int best = -1;
+    float best_ms = 1e30f;
+    const int reps = 5;
+    for (int v = 0; v < V_COUNT; v++) {
+        hipError_t err = launch_stage(v, c->prec(), c->c12(), c->stream, c->d_desc(),
+                                      c->d_tiles(), n, ts[n], 0, 0, 0.01, 0);
+        if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && err == hipSuccess; r++)
+            err = launch_stage(v, c->prec(), c->c12(), c->stream, c->d_desc(), c->d_tiles(), n,
+                               ts[n], 0, 0, 0.01, 0);
+        if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms_ = 0;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms_, e0, e1);
+        if (err != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return fail(TGF_E_HIP, std::string("autotune: ") + hipGetErrorString(err));
+        }
+        if (ms_ < best_ms) { best_ms = ms_; best = v; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->variant = best;
+    if (cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        if (o) o << key << " " << best << "\n";
+    }
+    return TGF_OK;
+}
+
+tgf_status tgf_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, void *hip_stream) {
+    g_err.clear();
+    if (!dst_dev || !src_dev) return fail(TGF_E_INVAL, "NULL pointer");
+    if (((uintptr_t)dst_dev | (uintptr_t)src_dev | bytes) % 16)
+        return fail(TGF_E_INVAL, "pointers and size must be 16-byte aligned");
+    HIP_TRY(launch_copy((hipStream_t)hip_stream, dst_dev, src_dev, bytes));
+    return TGF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+"""GPU checks by properties that hold at any size (twist-eater, gauge
+covariance, unitarity, monotone action, FP32 vs the parity-checked FP64
+path), including the full benchmark sizes, and error handling on the device.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import fields                                      # noqa: E402
+from paper_2107_03747_amd import gen, tgf          # noqa: E402
+
+COL = {n: k for k, n in enumerate(tgf.OBS_FIELDS)}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32c12"])
+@pytest.mark.parametrize("dims", [(4, 4, 12, 12), (32, 32, 96, 96)])
+def test_twist_eater_is_fixed(dims, storage):
+    say(f"  twist eater {dims} {storage}")
+    if np.prod(dims) > 1e6:
+        U = gen.identity(dims, device="cuda")
+        Ga, Gb = (torch.from_numpy(m).cuda() for m in fields.twist_matrices())
+        U[:, :, :, 0, 0] = Ga
+        U[:, :, 0, :, 1] = Gb
+    else:
+        U = torch.from_numpy(fields.twist_eater(dims)).cuda()
+    f = tgf.Flow([dims], storage)
+    f.load(0, U)
+    rows = f.flow(0.01, 0.03, 0.01, reunit=1)
+    tol = 1e-13 if storage == "f64" else 1e-5
+    assert np.abs(rows[:, 0, COL["E"]]).max() < tol ** 2 * 10
+    assert np.abs(rows[:, 0, COL["plaq"]] - 1).max() < tol
+    assert np.abs(rows[:, 0, COL["Q"]]).max() < tol
+    assert (f.store(0) - U).abs().max().item() < (1e-14 if storage == "f64" else 1e-6)
+    del U
+
+
+def test_gauge_covariance_gpu():
+    dims = (8, 8, 24, 24)
+    U = gen.near_identity(dims, 0.5, seed=21).numpy().copy()
+    Lam = fields.su3_field(fields.shape(dims), seed=22)
+    Ug = fields.gauge_transform(U, Lam)
+    f = tgf.Flow([dims, dims], "f64")
+    f.load_all([torch.from_numpy(U).cuda(), torch.from_numpy(Ug).cuda()])
+    rows = f.flow(0.01, 0.1, 0.05)
+    assert np.allclose(rows[:, 0, 1:], rows[:, 1, 1:], rtol=1e-12, atol=1e-12)
+    V0 = f.store(0).cpu().numpy()
+    V1 = f.store(1).cpu().numpy()
+    assert np.abs(fields.gauge_transform(V0, Lam) - V1).max() < 1e-12
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32c12"])
+def test_fp32_tracks_fp64_full_flow_d3(storage):
+    """16x16x48x48 Haar hot start flowed to c = 0.3 (t = 2.88, 288 steps)
+    in FP32 (reunitarised every 10 steps) against the FP64 GPU path."""
+    dims = (16, 16, 48, 48)
+    U = gen.haar(dims, seed=3, device="cuda")
+    say(f"  D3 full flow f64 vs {storage}")
+    a = tgf.Flow([dims], "f64")
+    a.load(0, U)
+    ra = a.flow(0.01, 2.88, 0.1)
+    b = tgf.Flow([dims], storage)
+    b.load(0, U)
+    rb = b.flow(0.01, 2.88, 0.1, reunit=10)
+    pos = ra[:, 0, 0] > 0
+    rel = np.abs(rb[pos, 0, COL["t2E"]] - ra[pos, 0, COL["t2E"]]) / ra[pos, 0, COL["t2E"]]
+    say(f"  max rel t2E {rel.max():.3g}  final t2E {ra[-1, 0, COL['t2E']]:.6f} "
+        f"Q {ra[-1, 0, COL['Q']]:.4f} vs {rb[-1, 0, COL['Q']]:.4f}")
+    assert rel.max() <= 1e-5
+    assert np.all(np.diff(ra[:, 0, COL["action"]]) <= 1e-12 * ra[0, 0, COL["action"]])
+    du, dd = b.unitarity(0)
+    assert du < 2e-6 and dd < 2e-6
+
+
+def test_large_box_properties():
+    """32x32x96x96 (9.4M sites): FP32 C12 vs FP64 over the first 0.1 of flow
+    time, unitarity, monotone action."""
+    dims = (32, 32, 96, 96)
+    U = gen.haar(dims, seed=5, device="cuda")
+    say("  D5 f64")
+    a = tgf.Flow([dims], "f64")
+    a.load(0, U)
+    ra = a.flow(0.01, 0.1, 0.05)
+    du, dd = a.unitarity(0)
+    assert du < 1e-13 and dd < 1e-13
+    del a
+    say("  D5 f32c12")
+    b = tgf.Flow([dims], "f32c12")
+    b.load(0, U)
+    rb = b.flow(0.01, 0.1, 0.05, reunit=10)
+    rel = np.abs(rb[1:, 0, COL["t2E"]] - ra[1:, 0, COL["t2E"]]) / ra[1:, 0, COL["t2E"]]
+    say(f"  D5 max rel t2E {rel.max():.3g}")
+    assert rel.max() <= 1e-5
+    assert np.all(np.diff(ra[:, 0, COL["action"]]) < 0)
+
+
+def test_rejects_non_su3_and_nan():
+    dims = (4, 4, 12, 12)
+    U = torch.from_numpy(gen.near_identity(dims, 0.3, seed=1).numpy().copy()).cuda()
+    f = tgf.Flow([dims], "f32c12")
+    bad = U.clone()
+    bad[1, 2, 3, 0, 2] *= 1.001
+    with pytest.raises(tgf.TGFError) as e:
+        f.load(0, bad)
+    assert e.value.status == tgf.TGF_E_NOT_SU3
+    bad = U.clone()
+    bad[0, 0, 0, 0, 1, 1, 1] = float("nan")
+    with pytest.raises(tgf.TGFError) as e:
+        f.load(0, bad)
+    assert e.value.status == tgf.TGF_E_NOT_SU3
+    with pytest.raises(tgf.TGFError) as e:
+        f.flow(0.01, 0.1)
+    assert e.value.status == tgf.TGF_E_STATE
+    f.load(0, U)
+    f.flow(0.01, 0.02)
+    with pytest.raises(tgf.TGFError) as e:
+        f.flow(0.01, 0.01)       # t_end before the current time
+    assert e.value.status == tgf.TGF_E_INVAL
+
+
+def test_stream_copy():
+    x = torch.randn(1 << 20, device="cuda")
+    y = torch.empty_like(x)
+    tgf.stream_copy(y, x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
