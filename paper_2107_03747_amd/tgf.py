@@ -21,7 +21,34 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
                       "`python -m paper_2107_03747_amd.build` (hipcc, gfx950)")
 
+# torch ships its own HIP runtime with the same SONAME (libamdhip64.so.7) as
+# the ROCm one libtgf.so links against.  Loading torch first makes libtgf.so
+# bind to that same runtime, so device pointers and streams from torch are
+# valid in the library; the other order would map two runtimes.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:       # the library itself does not need torch
+    _torch = None
+
 _lib = ctypes.CDLL(LIB_PATH)
+
+
+def _hip_runtimes():
+    paths = set()
+    try:
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                p = line.split()[-1]
+                if "libamdhip64" in os.path.basename(p):
+                    paths.add(os.path.realpath(p))
+    except OSError:
+        pass
+    return paths
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are mapped in this process "
+                      f"({sorted(_hip_runtimes())}); import torch before loading libtgf.so")
 
 # --- status / enums -----------------------------------------------------------
 TGF_OK = 0

@@ -34,7 +34,7 @@ def test_twist_eater_is_fixed(dims, storage):
         U = torch.from_numpy(fields.twist_eater(dims)).cuda()
     f = tgf.Flow([dims], storage)
     f.load(0, U)
-    rows = f.flow(0.01, 0.03, 0.01, reunit=1)
+    rows = f.flow(0.01, 0.03, 0.01, reunit_every=1)
     tol = 1e-13 if storage == "f64" else 1e-5
     assert np.abs(rows[:, 0, COL["E"]]).max() < tol ** 2 * 10
     assert np.abs(rows[:, 0, COL["plaq"]] - 1).max() < tol
@@ -69,15 +69,18 @@ def test_fp32_tracks_fp64_full_flow_d3(storage):
     ra = a.flow(0.01, 2.88, 0.1)
     b = tgf.Flow([dims], storage)
     b.load(0, U)
-    rb = b.flow(0.01, 2.88, 0.1, reunit=10)
+    rb = b.flow(0.01, 2.88, 0.1, reunit_every=10)
     pos = ra[:, 0, 0] > 0
     rel = np.abs(rb[pos, 0, COL["t2E"]] - ra[pos, 0, COL["t2E"]]) / ra[pos, 0, COL["t2E"]]
     say(f"  max rel t2E {rel.max():.3g}  final t2E {ra[-1, 0, COL['t2E']]:.6f} "
         f"Q {ra[-1, 0, COL['Q']]:.4f} vs {rb[-1, 0, COL['Q']]:.4f}")
     assert rel.max() <= 1e-5
     assert np.all(np.diff(ra[:, 0, COL["action"]]) <= 1e-12 * ra[0, 0, COL["action"]])
+    # unitarity after up to 10 steps (30 single-precision link updates of a few
+    # ulp = 2^-24 each) since the last FP64 reunitarisation, maximised over
+    # 2.4M links: a few-sigma random walk of ~1e-6
     du, dd = b.unitarity(0)
-    assert du < 2e-6 and dd < 2e-6
+    assert du < 1e-5 and dd < 1e-5
 
 
 def test_large_box_properties():
@@ -95,7 +98,7 @@ def test_large_box_properties():
     say("  D5 f32c12")
     b = tgf.Flow([dims], "f32c12")
     b.load(0, U)
-    rb = b.flow(0.01, 0.1, 0.05, reunit=10)
+    rb = b.flow(0.01, 0.1, 0.05, reunit_every=10)
     rel = np.abs(rb[1:, 0, COL["t2E"]] - ra[1:, 0, COL["t2E"]]) / ra[1:, 0, COL["t2E"]]
     say(f"  D5 max rel t2E {rel.max():.3g}")
     assert rel.max() <= 1e-5
