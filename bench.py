@@ -95,12 +95,14 @@ def make_inputs(cfgs, device):
 
 
 def time_flows(tgf, torch, cfgs, inputs, storage, steps, warmup, flags=0, reunit=10,
-               autotune=True):
+               variant=None):
     t_end = [c[3] for c in cfgs]
     f = tgf.Flow([c[0] for c in cfgs], storage)
     f.load_all(inputs)
-    if autotune:
+    if variant is None:
         f.autotune(None)
+    else:
+        f.set_variant(variant)
 
     def one():
         f.load_all(inputs)
@@ -190,9 +192,7 @@ def main():
 
     log(f"timing {args.storage}: {args.warmup} warmup + {args.steps} steps")
     f, rows, dt = time_flows(tgf, torch, cfgs, inputs, args.storage, args.steps, args.warmup,
-                             autotune=args.variant is None)
-    if args.variant is not None:
-        f.set_variant(args.variant)
+                             variant=args.variant)
     variant = tgf.variant_names()[f.variant]
     value = site_updates / dt
 

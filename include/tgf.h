@@ -98,12 +98,16 @@ typedef struct {
     uint32_t flags;        /* TGF_NO_GRAPH | TGF_TIMING */
 } tgf_flow_params;
 
-/* Kernel time of the last tgf_flow run with TGF_TIMING. */
+/* Kernel time of the last tgf_flow run with TGF_TIMING (HIP events around
+ * every launch on the context's stream). */
 typedef struct {
-    double stage_ms;          /* total duration of the RK stage kernels */
-    int64_t stage_launches;   /* number of RK stage launches */
-    double stage_bytes;       /* algorithmic HBM bytes moved by those launches */
+    double stage_ms;          /* total duration of the RK stage (force + update) kernels */
+    int64_t stage_launches;   /* number of those launches (one per stage) */
+    double stage_bytes;       /* algorithmic HBM bytes of those launches */
     double stage_site_updates;/* site-stage updates / 3 (= site-updates) */
+    double aux_ms;            /* plaquette-algebra kernels of the split variants */
+    int64_t aux_launches;
+    double aux_bytes;         /* their algorithmic HBM bytes */
     double measure_ms;        /* measurement + reduction kernels */
     int64_t measure_launches;
 } tgf_timing;

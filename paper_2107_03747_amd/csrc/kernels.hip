@@ -30,6 +30,42 @@ namespace tgf {
 
 constexpr int kTile = 64;
 
+// Pointers into the workspace in the global address space: loads and stores
+// become global_* instructions with a uniform (SGPR) base and a 32-bit
+// per-lane offset, instead of flat instructions with 64-bit per-lane addresses.
+// The element type is a built-in two-lane vector (re, im) with the size and
+// alignment of cx<R>, so a complex number moves with one 8- or 16-byte access.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class R>
+using v2 = R __attribute__((ext_vector_type(2)));
+
+template <class R>
+__device__ __forceinline__ gptr<v2<R>> as_global(void *p) {
+    return (gptr<v2<R>>)p;
+}
+template <class R>
+__device__ __forceinline__ gptr<const v2<R>> as_global(const void *p) {
+    return (gptr<const v2<R>>)p;
+}
+template <class R>
+__device__ __forceinline__ cx<R> ld(gptr<const v2<R>> q, size_t k) {
+    v2<R> v = q[k];
+    return {v.x, v.y};
+}
+template <class R>
+__device__ __forceinline__ cx<R> ld(gptr<v2<R>> q, size_t k) {
+    v2<R> v = q[k];
+    return {v.x, v.y};
+}
+template <class R>
+__device__ __forceinline__ void st(gptr<v2<R>> q, size_t k, cx<R> z) {
+    v2<R> v;
+    v.x = z.x;
+    v.y = z.y;
+    q[k] = v;
+}
+
 // ---------------------------------------------------------------------------
 // geometry
 
@@ -107,21 +143,23 @@ __device__ __forceinline__ int find_cfg(const int *__restrict__ tile_start, int 
 
 template <class R, int NE>
 struct Links {
-    const cx<R> *__restrict__ p;
+    gptr<const v2<R>> p;
     int stride;
     __device__ __forceinline__ M3<R> operator()(int mu, int i) const {
-        const cx<R> *q = p + (size_t)(mu * NE) * stride + i;
+        // entry planes are uniform bases, the site index the lane offset
+        gptr<const v2<R>> q = p + (size_t)(mu * NE) * stride;
+        const unsigned u = (unsigned)i;
         M3<R> U;
-        U.e[0][0] = q[0];
-        U.e[0][1] = q[(size_t)stride];
-        U.e[0][2] = q[(size_t)2 * stride];
-        U.e[1][0] = q[(size_t)3 * stride];
-        U.e[1][1] = q[(size_t)4 * stride];
-        U.e[1][2] = q[(size_t)5 * stride];
+        U.e[0][0] = ld(q, u);
+        U.e[0][1] = ld(q, (size_t)stride + u);
+        U.e[0][2] = ld(q, (size_t)2 * stride + u);
+        U.e[1][0] = ld(q, (size_t)3 * stride + u);
+        U.e[1][1] = ld(q, (size_t)4 * stride + u);
+        U.e[1][2] = ld(q, (size_t)5 * stride + u);
         if constexpr (NE == 9) {
-            U.e[2][0] = q[(size_t)6 * stride];
-            U.e[2][1] = q[(size_t)7 * stride];
-            U.e[2][2] = q[(size_t)8 * stride];
+            U.e[2][0] = ld(q, (size_t)6 * stride + u);
+            U.e[2][1] = ld(q, (size_t)7 * stride + u);
+            U.e[2][2] = ld(q, (size_t)8 * stride + u);
         } else {
             rebuild_row2(U);
         }
@@ -130,19 +168,20 @@ struct Links {
 };
 
 template <class R, int NE>
-__device__ __forceinline__ void store_link(cx<R> *__restrict__ p, int stride, int mu, int i,
+__device__ __forceinline__ void store_link(gptr<v2<R>> p, int stride, int mu, int i,
                                            const M3<R> &U) {
-    cx<R> *q = p + (size_t)(mu * NE) * stride + i;
-    q[0] = U.e[0][0];
-    q[(size_t)stride] = U.e[0][1];
-    q[(size_t)2 * stride] = U.e[0][2];
-    q[(size_t)3 * stride] = U.e[1][0];
-    q[(size_t)4 * stride] = U.e[1][1];
-    q[(size_t)5 * stride] = U.e[1][2];
+    gptr<v2<R>> q = p + (size_t)(mu * NE) * stride;
+    const unsigned u = (unsigned)i;
+    st(q, u, U.e[0][0]);
+    st(q, (size_t)stride + u, U.e[0][1]);
+    st(q, (size_t)2 * stride + u, U.e[0][2]);
+    st(q, (size_t)3 * stride + u, U.e[1][0]);
+    st(q, (size_t)4 * stride + u, U.e[1][1]);
+    st(q, (size_t)5 * stride + u, U.e[1][2]);
     if constexpr (NE == 9) {
-        q[(size_t)6 * stride] = U.e[2][0];
-        q[(size_t)7 * stride] = U.e[2][1];
-        q[(size_t)8 * stride] = U.e[2][2];
+        st(q, (size_t)6 * stride + u, U.e[2][0]);
+        st(q, (size_t)7 * stride + u, U.e[2][1]);
+        st(q, (size_t)8 * stride + u, U.e[2][2]);
     }
 }
 
@@ -235,25 +274,26 @@ __device__ __forceinline__ M3<R> lower_staple(const Links<R, NE> &W, const CfgDe
 
 // RK stage tail for one link: X = B eps F + A X_old; W_out = exp(X) W_in.
 template <class R, int NE>
-__device__ __forceinline__ void update_link(const Links<R, NE> &W, cx<R> *__restrict__ Wout,
-                                            cx<R> *__restrict__ X, int stride, int mu, int i,
+__device__ __forceinline__ void update_link(const Links<R, NE> &W, gptr<v2<R>> Wout,
+                                            gptr<v2<R>> X, int stride, int mu, int i,
                                             const M3<R> &Omega, R beps, R a, int stage,
                                             int reunit) {
     Alg<R> Z = proj_ah(Omega, -beps);
-    cx<R> *xp = X + (size_t)(mu * 4) * stride + i;
+    gptr<v2<R>> xp = X + (size_t)(mu * 4) * stride;
+    const unsigned u = (unsigned)i;
     if (stage > 0) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            cx<R> o = xp[(size_t)k * stride];
+            cx<R> o = ld(xp, (size_t)k * stride + u);
             Z.a[2 * k] = fma(a, o.x, Z.a[2 * k]);
             Z.a[2 * k + 1] = fma(a, o.y, Z.a[2 * k + 1]);
         }
     }
     if (stage < 2) {
 #pragma unroll
-        for (int k = 0; k < 4; k++) xp[(size_t)k * stride] = cx<R>{Z.a[2 * k], Z.a[2 * k + 1]};
+        for (int k = 0; k < 4; k++) st(xp, (size_t)k * stride + u, cx<R>{Z.a[2 * k], Z.a[2 * k + 1]});
     }
-    M3<R> E = su3_exp(Z);
+    M3<R> E = su3_exp<R, NE == 9 ? 3 : 2>(Z);
     M3<R> U = W(mu, i);
     M3<R> N;
     if constexpr (NE == 9) {
@@ -310,9 +350,9 @@ __global__ __launch_bounds__(256) void stage_site_kernel(StageArgs a) {
     if (i >= c.V) return;
 
     const int in = (c.cur + 3 * a.step + a.stage) & 1;
-    const Links<R, NE> W{(const cx<R> *)c.W[in], c.stride};
-    cx<R> *Wout = (cx<R> *)c.W[in ^ 1];
-    cx<R> *X = (cx<R> *)c.X;
+    const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
+    gptr<v2<R>> Wout = as_global<R>(in ? c.W[0] : c.W[1]);
+    gptr<v2<R>> X = as_global<R>(c.X);
     const double eps = a.step < c.n_full ? a.eps : c.eps_last;
     const R beps = (R)(kRkB[a.stage] * eps);
     const R ac = (R)kRkA[a.stage];
@@ -350,9 +390,9 @@ __global__ __launch_bounds__(256) void stage_site_kernel(StageArgs a) {
 template <class R, int NE, int MU>
 __device__ __forceinline__ void link_body(const StageArgs &a, const CfgDesc &c, int i) {
     const int in = (c.cur + 3 * a.step + a.stage) & 1;
-    const Links<R, NE> W{(const cx<R> *)c.W[in], c.stride};
-    cx<R> *Wout = (cx<R> *)c.W[in ^ 1];
-    cx<R> *X = (cx<R> *)c.X;
+    const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
+    gptr<v2<R>> Wout = as_global<R>(in ? c.W[0] : c.W[1]);
+    gptr<v2<R>> X = as_global<R>(c.X);
     const double eps = a.step < c.n_full ? a.eps : c.eps_last;
     const R beps = (R)(kRkB[a.stage] * eps);
     const R ac = (R)kRkA[a.stage];
@@ -385,6 +425,151 @@ __global__ __launch_bounds__(256) void stage_link_kernel(StageArgs a) {
         case 1: link_body<R, NE, 1>(a, c, i); break;
         case 2: link_body<R, NE, 2>(a, c, i); break;
         default: link_body<R, NE, 3>(a, c, i); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// split stage: the force projection is linear and commutes with conjugation,
+//   P_ah(Omega_mu(n)) = sum_{nu != mu} [ A_{mu nu}(n) - U_nu(n-nu)^+ A_{mu nu}(n-nu) U_nu(n-nu) ],
+//   A_{mu nu}(n) = P_ah(Z^*_{mu nu}(n) P_{mu nu}(n)),  A_{nu mu} = -A_{mu nu},
+// because the lower staple term of Omega_mu(n) is the plaquette
+// Z^* P_{mu nu}(n-nu), adjoined and conjugated by U_nu(n-nu).  Part 0 writes
+// the six A_{mu nu}(n) of every site once per stage (each plaquette is built
+// once per lattice instead of up to four times); part 1 forms the force of
+// every link from three own and three neighbouring A and updates the link.
+
+template <class R>
+__device__ __forceinline__ void r2_scale(R2<R> &A, cx<R> z) {
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) A.e[i][j] = cmul(z, A.e[i][j]);
+}
+
+template <class R, int NE>
+__global__ __launch_bounds__(256) void plaq_alg_kernel(StageArgs a) {
+    const int nb = (a.n_tiles + 3) >> 2;
+    const int b = remap_block(blockIdx.x, nb, a.xcd);
+    if (b >= nb) return;
+    const int tile = b * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= a.n_tiles) return;
+    const int ci = find_cfg(a.tile_start, a.n_act, tile);
+    const CfgDesc c = a.cfgs[ci];
+    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
+    if (i >= c.V) return;
+    const int in = (c.cur + 3 * a.step + a.stage) & 1;
+    const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
+    gptr<v2<R>> Ap = as_global<R>(c.A);
+    const Geo g = make_geo(c, i);
+    const unsigned u = (unsigned)i;
+#pragma unroll
+    for (int mu = 0, p = 0; mu < 4; mu++)
+#pragma unroll
+        for (int nu = mu + 1; nu < 4; nu++, p++) {
+            // rows 0,1 of U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
+            R2<R> P = r2_of(W(mu, i));
+            P = r2_mul_nn(P, W(nu, i + g.up(mu)));
+            P = r2_mul_nd(P, W(mu, i + g.up(nu)));
+            P = r2_mul_nd(P, W(nu, i));
+            const int k = c.tw[p];
+            if (k && g.n[mu] == 0 && g.n[nu] == 0) r2_scale(P, cconj(omega_pow<R>(k)));
+            R A8[8];
+            r2_proj_ah(P, R(1), A8);
+            gptr<v2<R>> q = Ap + (size_t)(p * 4) * c.stride;
+#pragma unroll
+            for (int t = 0; t < 4; t++) st(q, (size_t)t * c.stride + u, cx<R>{A8[2 * t], A8[2 * t + 1]});
+        }
+}
+
+template <class R>
+__device__ __forceinline__ void load_alg(gptr<const v2<R>> Ap, int stride, int p, int i, R out[8]) {
+    gptr<const v2<R>> q = Ap + (size_t)(p * 4) * stride;
+    const unsigned u = (unsigned)i;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        cx<R> v = ld(q, (size_t)t * stride + u);
+        out[2 * t] = v.x;
+        out[2 * t + 1] = v.y;
+    }
+}
+
+template <class R, int NE, int MU>
+__device__ __forceinline__ void split_body(const StageArgs &a, const CfgDesc &c, int i) {
+    const int in = (c.cur + 3 * a.step + a.stage) & 1;
+    const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
+    gptr<v2<R>> Wout = as_global<R>(in ? c.W[0] : c.W[1]);
+    gptr<v2<R>> X = as_global<R>(c.X);
+    gptr<const v2<R>> Ap = as_global<R>((const void *)c.A);
+    const double eps = a.step < c.n_full ? a.eps : c.eps_last;
+    const R beps = (R)(kRkB[a.stage] * eps);
+    const R ac = (R)kRkA[a.stage];
+    const Geo g = make_geo(c, i);
+
+    R om[8];   // P_ah(Omega_mu(n))
+#pragma unroll
+    for (int t = 0; t < 8; t++) om[t] = R(0);
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == MU) continue;
+        const int p = MU < nu ? plane_index(MU, nu) : plane_index(nu, MU);
+        const R sg = MU < nu ? R(1) : R(-1);
+        R up[8], lo[8], cl[8];
+        load_alg(Ap, c.stride, p, i, up);
+        const int m = i + g.dn(nu);
+        load_alg(Ap, c.stride, p, m, lo);
+        conj_alg(W(nu, m), lo, cl);
+#pragma unroll
+        for (int t = 0; t < 8; t++) om[t] = fma(sg, up[t] - cl[t], om[t]);
+    }
+    // X = B eps F + A X_old with F = -P_ah(Omega)
+    Alg<R> Z;
+#pragma unroll
+    for (int t = 0; t < 8; t++) Z.a[t] = -beps * om[t];
+    gptr<v2<R>> xp = X + (size_t)(MU * 4) * c.stride;
+    const unsigned u = (unsigned)i;
+    if (a.stage > 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            cx<R> o = ld(xp, (size_t)k * c.stride + u);
+            Z.a[2 * k] = fma(ac, o.x, Z.a[2 * k]);
+            Z.a[2 * k + 1] = fma(ac, o.y, Z.a[2 * k + 1]);
+        }
+    }
+    if (a.stage < 2) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) st(xp, (size_t)k * c.stride + u, cx<R>{Z.a[2 * k], Z.a[2 * k + 1]});
+    }
+    const M3<R> E = su3_exp<R, NE == 9 ? 3 : 2>(Z);
+    const M3<R> U = W(MU, i);
+    M3<R> N;
+    if constexpr (NE == 9) {
+        N = mul_nn(E, U);
+    } else {
+        R2<R> r = r2_mul_nn(r2_of(E), U);
+#pragma unroll
+        for (int rr = 0; rr < 2; rr++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) N.e[rr][j] = r.e[rr][j];
+    }
+    if (a.reunit) reunitarise(N);
+    store_link<R, NE>(Wout, c.stride, MU, i, N);
+}
+
+template <class R, int NE>
+__global__ __launch_bounds__(256) void split_link_kernel(StageArgs a) {
+    const int b = remap_block(blockIdx.x, a.n_tiles, a.xcd);
+    if (b >= a.n_tiles) return;
+    const int tile = b;
+    const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ci = find_cfg(a.tile_start, a.n_act, tile);
+    const CfgDesc c = a.cfgs[ci];
+    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
+    if (i >= c.V) return;
+    switch (mu) {
+        case 0: split_body<R, NE, 0>(a, c, i); break;
+        case 1: split_body<R, NE, 1>(a, c, i); break;
+        case 2: split_body<R, NE, 2>(a, c, i); break;
+        default: split_body<R, NE, 3>(a, c, i); break;
     }
 }
 
@@ -486,7 +671,7 @@ __global__ __launch_bounds__(256) void measure_kernel(const CfgDesc *__restrict_
     double e = 0, q = 0, p = 0, s = 0;
     if (i < c.V) {
         const int sel = buf_sel < 0 ? c.cur : ((c.cur + buf_sel) & 1);
-        const Links<R, NE> W{(const cx<R> *)c.W[sel], c.stride};
+        const Links<R, NE> W{as_global<R>((const void *)(sel ? c.W[1] : c.W[0])), c.stride};
         const Geo g = make_geo(c, i);
         // planes in dual pairs: (01,23), (02,13), (03,12); q picks up
         // Tr G01 G23 - Tr G02 G13 + Tr G03 G12
@@ -701,35 +886,42 @@ const char *variant_name(int v) {
         case V_LINK: return "link";
         case V_SITE_XCD: return "site_xcd";
         case V_LINK_XCD: return "link_xcd";
+        case V_SPLIT: return "split";
+        case V_SPLIT_XCD: return "split_xcd";
         default: return "?";
     }
 }
 
 template <class R, int NE>
-static hipError_t launch_stage_t(int variant, hipStream_t s, const StageArgs &a) {
-    const bool xcd = variant == V_SITE_XCD || variant == V_LINK_XCD;
+static hipError_t launch_stage_t(int variant, int part, hipStream_t s, const StageArgs &a) {
+    const bool xcd = variant == V_SITE_XCD || variant == V_LINK_XCD || variant == V_SPLIT_XCD;
     StageArgs b = a;
     b.xcd = xcd ? 1 : 0;
-    if (variant == V_SITE || variant == V_SITE_XCD) {
-        int nb = (a.n_tiles + 3) / 4;
-        if (xcd) nb = ((nb + 7) / 8) * 8;
-        hipLaunchKernelGGL((stage_site_kernel<R, NE>), dim3(nb), dim3(256), 0, s, b);
+    const int site_blocks = xcd ? ((a.n_tiles + 3) / 4 + 7) / 8 * 8 : (a.n_tiles + 3) / 4;
+    const int tile_blocks = xcd ? (a.n_tiles + 7) / 8 * 8 : a.n_tiles;
+    if (variant_is_split(variant)) {
+        if (part == 0)
+            hipLaunchKernelGGL((plaq_alg_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
+        else
+            hipLaunchKernelGGL((split_link_kernel<R, NE>), dim3(tile_blocks), dim3(256), 0, s, b);
+    } else if (part == 0) {
+        return hipSuccess;   // single-kernel variants have no part 0
+    } else if (variant == V_SITE || variant == V_SITE_XCD) {
+        hipLaunchKernelGGL((stage_site_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
     } else {
-        int nb = a.n_tiles;
-        if (xcd) nb = ((nb + 7) / 8) * 8;
-        hipLaunchKernelGGL((stage_link_kernel<R, NE>), dim3(nb), dim3(256), 0, s, b);
+        hipLaunchKernelGGL((stage_link_kernel<R, NE>), dim3(tile_blocks), dim3(256), 0, s, b);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_stage(int variant, Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
-                        const int *tile_start, int n_act, int n_tiles, int step, int stage,
-                        double eps, int reunit) {
+hipError_t launch_stage(int variant, int part, Prec p, bool c12, hipStream_t s,
+                        const CfgDesc *cfgs, const int *tile_start, int n_act, int n_tiles,
+                        int step, int stage, double eps, int reunit) {
     if (n_tiles <= 0) return hipSuccess;
     StageArgs a{cfgs, tile_start, n_act, n_tiles, step, stage, eps, reunit, 0};
-    if (p == P_F64) return launch_stage_t<double, 9>(variant, s, a);
-    if (c12) return launch_stage_t<float, 6>(variant, s, a);
-    return launch_stage_t<float, 9>(variant, s, a);
+    if (p == P_F64) return launch_stage_t<double, 9>(variant, part, s, a);
+    if (c12) return launch_stage_t<float, 6>(variant, part, s, a);
+    return launch_stage_t<float, 9>(variant, part, s, a);
 }
 
 hipError_t launch_measure(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,

@@ -16,15 +16,21 @@ enum Variant {
     V_LINK = 1,       // one thread per link (wave-uniform mu), no sharing
     V_SITE_XCD = 2,   // V_SITE with XCD-contiguous tile order
     V_LINK_XCD = 3,   // V_LINK with XCD-contiguous tile order
-    V_COUNT = 4
+    V_SPLIT = 4,      // two kernels per stage: plaquette algebra A_{mu nu}(n), then
+                      // force from A and its conjugated neighbours + update
+    V_SPLIT_XCD = 5,  // V_SPLIT with XCD-contiguous tile order
+    V_COUNT = 6
 };
+inline bool variant_is_split(int v) { return v == V_SPLIT || v == V_SPLIT_XCD; }
 const char *variant_name(int v);
 
 // All launchers enqueue on `s` and return the hipError_t of the launch.
 // `tile_start` has n_act+1 entries (exec order); tiles are 64 sites.
-hipError_t launch_stage(int variant, Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
-                        const int *tile_start, int n_act, int n_tiles, int step, int stage,
-                        double eps, int reunit);
+// One RK stage is part 1 (staples/force + update) of the variant, preceded for
+// the split variants by part 0 (plaquette algebra).
+hipError_t launch_stage(int variant, int part, Prec p, bool c12, hipStream_t s,
+                        const CfgDesc *cfgs, const int *tile_start, int n_act, int n_tiles,
+                        int step, int stage, double eps, int reunit);
 
 hipError_t launch_measure(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
                           const int *tile_start, int n_cfg, int n_tiles, const MeasSlot *slots,

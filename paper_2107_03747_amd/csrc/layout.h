@@ -5,7 +5,11 @@
 //               [mu (4)][entry (NE)][site (stride)] of complex R, where NE = 9
 //               (full storage, row-major entries) or 6 (rows 0 and 1 only);
 //   X           RK accumulator [mu (4)][slot (4)][site (stride)] of complex R:
-//               slots 0..2 = X01, X02, X12, slot 3 = (Im X00, Im X11).
+//               slots 0..2 = X01, X02, X12, slot 3 = (Im X00, Im X11);
+//   A           plaquette algebra [plane (6)][slot (4)][site (stride)] of
+//               complex R, same slot format: A_{mu nu}(n) = P_ah(Z^* P_{mu nu}(n))
+//               for mu < nu (written and read within one RK stage by the
+//               two-kernel "split" stage variants).
 // `stride` is the site count rounded up to a multiple of 256 so that every
 // entry plane starts 256-byte aligned and a wavefront's 64 consecutive sites
 // read 64 consecutive complex numbers (fully coalesced).
@@ -35,6 +39,7 @@ struct CfgDesc {
     double t0;            // flow time at the start of this flow
     void *W[2];
     void *X;
+    void *A;
 };
 
 // Per-measurement-event schedule entry for one config (exec order).

@@ -51,7 +51,7 @@ struct CfgHost {
     int V;
     int stride;
     int tiles;
-    size_t offW[2], offX;
+    size_t offW[2], offX, offA;
     int cur = 0;
     double t = 0;
     bool loaded = false;
@@ -117,16 +117,18 @@ Layout make_layout(int32_t n_cfg, const tgf_geom *g, tgf_storage st) {
         CfgHost &h = L.cfg[c];
         size_t wb = e * 4 * NE * (size_t)h.stride;
         size_t xb = e * 4 * 4 * (size_t)h.stride;
+        size_t ab = e * 6 * 4 * (size_t)h.stride;
         h.offW[0] = o; o = align_up(o + wb, 256);
         h.offW[1] = o; o = align_up(o + wb, 256);
         h.offX = o;    o = align_up(o + xb, 256);
+        h.offA = o;    o = align_up(o + ab, 256);
     }
     L.total = o;
     return L;
 }
 
 struct Launch {
-    int kind;      // 0 stage, 1 measure, 2 finalize, 3 zero flag
+    int kind;      // 0 stage (part 1), 1 measure, 2 finalize, 3 zero flag, 4 stage part 0
     int grid;      // tiles (stage/measure) or configs (finalize)
     int n_act;
     int step, stage;
@@ -199,6 +201,7 @@ void fill_desc(const tgf_ctx *c, const CfgHost &h, int user, CfgDesc &d) {
     d.W[0] = c->ws + h.offW[0];
     d.W[1] = c->ws + h.offW[1];
     d.X = c->ws + h.offX;
+    d.A = c->ws + h.offA;
 }
 
 bool on_grid(double t, double dt) {
@@ -243,8 +246,10 @@ tgf_status run_launches(tgf_ctx *c, const std::vector<Launch> &ls, double eps, b
     auto issue = [&](const Launch &l) -> hipError_t {
         switch (l.kind) {
             case 0:
-                return launch_stage(variant, c->prec(), c->c12(), s, c->d_desc(), c->d_tiles(),
-                                    l.n_act, l.grid, l.step, l.stage, eps, l.reunit);
+            case 4:
+                return launch_stage(variant, l.kind == 0 ? 1 : 0, c->prec(), c->c12(), s,
+                                    c->d_desc(), c->d_tiles(), l.n_act, l.grid, l.step, l.stage,
+                                    eps, l.reunit);
             case 1:
                 return launch_measure(c->prec(), c->c12(), s, c->d_desc(), c->d_tiles(), l.n_act,
                                       l.grid, c->d_meas() + (size_t)l.event * c->n_cfg,
@@ -630,11 +635,14 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
     };
     add_meas(0);
     const bool fp32 = c->st != TGF_F64_FULL;
+    const bool split = variant_is_split(c->effective_variant());
     for (int k = 0; k < max_steps; k++) {
         int na = active[k];
         int reunit = (fp32 && p->reunit_every > 0 && (k + 1) % p->reunit_every == 0) ? 1 : 0;
-        for (int st = 0; st < 3; st++)
+        for (int st = 0; st < 3; st++) {
+            if (split) ls.push_back(Launch{4, ts[na], na, k, st, 0, -1});
             ls.push_back(Launch{0, ts[na], na, k, st, st == 2 ? reunit : 0, -1});
+        }
         add_meas(k + 1);
     }
 
@@ -661,15 +669,23 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
             float ms_ = 0;
             HIP_TRY(hipEventElapsedTime(&ms_, c->events[2 * k], c->events[2 * k + 1]));
             const Launch &l = ls[k];
+            double sites = 0;
+            if (l.kind == 0 || l.kind == 4)
+                for (int j = 0; j < l.n_act; j++) sites += c->L.cfg[order[j]].V;
+            // algorithmic bytes: every element an operation touches, once
+            const double links = 4.0 * NE * e, xs = 4.0 * 4 * e, as = 6.0 * 4 * e;
             if (l.kind == 0) {
                 tm.stage_ms += ms_;
                 tm.stage_launches++;
-                double sites = 0;
-                for (int j = 0; j < l.n_act; j++) sites += c->L.cfg[order[j]].V;
-                // links read + written, X written (stage 0), read+written (1), read (2)
+                // links read + written, X written (stage 0), read+written (1), read (2),
+                // and for the split variants the plaquette algebra read
                 double xfac = l.stage == 1 ? 2.0 : 1.0;
-                tm.stage_bytes += sites * (2.0 * 4 * NE * e + xfac * 4 * 4 * e);
+                tm.stage_bytes += sites * (2.0 * links + xfac * xs + (split ? as : 0.0));
                 tm.stage_site_updates += sites / 3.0;
+            } else if (l.kind == 4) {
+                tm.aux_ms += ms_;
+                tm.aux_launches++;
+                tm.aux_bytes += sites * (links + as);   // links read, A written
             } else if (l.kind == 1 || l.kind == 2) {
                 tm.measure_ms += ms_;
                 tm.measure_launches++;
@@ -778,13 +794,17 @@ tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path) {
     int best = -1;
     float best_ms = 1e30f;
     const int reps = 5;
+    auto stage0 = [&](int v) {
+        hipError_t err = hipSuccess;
+        for (int part = 0; part < 2 && err == hipSuccess; part++)
+            err = launch_stage(v, part, c->prec(), c->c12(), c->stream, c->d_desc(),
+                               c->d_tiles(), n, ts[n], 0, 0, 0.01, 0);
+        return err;
+    };
     for (int v = 0; v < V_COUNT; v++) {
-        hipError_t err = launch_stage(v, c->prec(), c->c12(), c->stream, c->d_desc(),
-                                      c->d_tiles(), n, ts[n], 0, 0, 0.01, 0);
+        hipError_t err = stage0(v);
         if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
-        for (int r = 0; r < reps && err == hipSuccess; r++)
-            err = launch_stage(v, c->prec(), c->c12(), c->stream, c->d_desc(), c->d_tiles(), n,
-                               ts[n], 0, 0, 0.01, 0);
+        for (int r = 0; r < reps && err == hipSuccess; r++) err = stage0(v);
         if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms_ = 0;

@@ -185,6 +185,123 @@ __device__ __forceinline__ Alg<R> proj_ah(const M3<R> &M, R s) {
     return X;
 }
 
+// ---------------------------------------------------------------------------
+// Two-row arithmetic for products that stay in SU(3): rows 0 and 1 of a
+// product are computed, the third row of an SU(3) matrix is conj(row0 x row1).
+
+template <class R>
+struct R2 {   // rows 0 and 1 of a 3x3 matrix
+    cx<R> e[2][3];
+};
+
+// rows 0,1 of A B (A given by its rows 0,1)
+template <class R>
+__device__ __forceinline__ R2<R> r2_mul_nn(const R2<R> &A, const M3<R> &B) {
+    R2<R> C;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            cx<R> s = cmul(A.e[i][0], B.e[0][j]);
+            s = cmadd(s, A.e[i][1], B.e[1][j]);
+            s = cmadd(s, A.e[i][2], B.e[2][j]);
+            C.e[i][j] = s;
+        }
+    return C;
+}
+
+// rows 0,1 of A B^+
+template <class R>
+__device__ __forceinline__ R2<R> r2_mul_nd(const R2<R> &A, const M3<R> &B) {
+    R2<R> C;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            cx<R> s = {R(0), R(0)};
+            s = cmadd_nc(s, A.e[i][0], B.e[j][0]);
+            s = cmadd_nc(s, A.e[i][1], B.e[j][1]);
+            s = cmadd_nc(s, A.e[i][2], B.e[j][2]);
+            C.e[i][j] = s;
+        }
+    return C;
+}
+
+template <class R>
+__device__ __forceinline__ R2<R> r2_of(const M3<R> &A) {
+    R2<R> r;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) r.e[i][j] = A.e[i][j];
+    return r;
+}
+
+// s * P_ah(P) for P in SU(3) given by rows 0,1; the entries of row 2 that the
+// projection needs (P20, P21, Im P22) come from row2 = conj(row0 x row1).
+template <class R>
+__device__ __forceinline__ void r2_proj_ah(const R2<R> &P, R s, R out[8]) {
+    const cx<R> *a = P.e[0], *b = P.e[1];
+    cx<R> p20 = cconj(csub(cmul(a[1], b[2]), cmul(a[2], b[1])));
+    cx<R> p21 = cconj(csub(cmul(a[2], b[0]), cmul(a[0], b[2])));
+    // Im P22 = -Im(a0 b1 - a1 b0)
+    R im22 = -((a[0].x * b[1].y + a[0].y * b[1].x) - (a[1].x * b[0].y + a[1].y * b[0].x));
+    R h = R(0.5) * s;
+    out[0] = h * (a[1].x - b[0].x);
+    out[1] = h * (a[1].y + b[0].y);
+    out[2] = h * (a[2].x - p20.x);
+    out[3] = h * (a[2].y + p20.y);
+    out[4] = h * (b[2].x - p21.x);
+    out[5] = h * (b[2].y + p21.y);
+    R tr3 = (a[0].y + b[1].y + im22) * R(1.0 / 3.0);
+    out[6] = s * (a[0].y - tr3);
+    out[7] = s * (b[1].y - tr3);
+}
+
+// C = U^+ A U for A in su(3) (8-real form); the result is again in su(3).
+template <class R>
+__device__ __forceinline__ void conj_alg(const M3<R> &U, const R a[8], R c[8]) {
+    // A as a matrix
+    const cx<R> x01 = {a[0], a[1]}, x02 = {a[2], a[3]}, x12 = {a[4], a[5]};
+    const R d0 = a[6], d1 = a[7], d2 = -(a[6] + a[7]);
+    M3<R> B;   // B = A U
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        // row 0: i d0 U0j + x01 U1j + x02 U2j
+        cx<R> t = {-d0 * U.e[0][j].y, d0 * U.e[0][j].x};
+        t = cmadd(t, x01, U.e[1][j]);
+        t = cmadd(t, x02, U.e[2][j]);
+        B.e[0][j] = t;
+        // row 1: -conj(x01) U0j + i d1 U1j + x12 U2j
+        t = {-d1 * U.e[1][j].y, d1 * U.e[1][j].x};
+        t = cmadd(t, cx<R>{-x01.x, x01.y}, U.e[0][j]);
+        t = cmadd(t, x12, U.e[2][j]);
+        B.e[1][j] = t;
+        // row 2: -conj(x02) U0j - conj(x12) U1j + i d2 U2j
+        t = {-d2 * U.e[2][j].y, d2 * U.e[2][j].x};
+        t = cmadd(t, cx<R>{-x02.x, x02.y}, U.e[0][j]);
+        t = cmadd(t, cx<R>{-x12.x, x12.y}, U.e[1][j]);
+        B.e[2][j] = t;
+    }
+    // C = U^+ B: upper off-diagonals and Im of the first two diagonal entries
+    const int ia[3] = {0, 0, 1}, ib[3] = {1, 2, 2};
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+        cx<R> s = {R(0), R(0)};
+#pragma unroll
+        for (int k = 0; k < 3; k++) s = cmadd_cn(s, U.e[k][ia[t]], B.e[k][ib[t]]);
+        c[2 * t] = s.x;
+        c[2 * t + 1] = s.y;
+    }
+#pragma unroll
+    for (int d = 0; d < 2; d++) {
+        R im = 0;
+#pragma unroll
+        for (int k = 0; k < 3; k++) im = fma(U.e[k][d].x, B.e[k][d].y, fma(-U.e[k][d].y, B.e[k][d].x, im));
+        c[6 + d] = im;
+    }
+}
+
 template <class R>
 struct ExpTol;
 template <>
@@ -198,6 +315,12 @@ struct ExpTol<double> {
     static constexpr int kmax = 24;
 };
 
+// 1/k for the exponential series (k = 0 unused)
+__device__ constexpr double kInvK[25] = {
+    0.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6, 1.0 / 7, 1.0 / 8, 1.0 / 9,
+    1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17,
+    1.0 / 18, 1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24};
+
 // exp(X) for X in su(3), by Cayley-Hamilton: with Q = -i X (Hermitian,
 // traceless), Q^3 = c1 Q + c0 with c1 = Tr(Q^2)/2, c0 = det Q, so every power
 // Q^k = alpha_k + beta_k Q + gamma_k Q^2 and exp(iQ) = f0 + f1 Q + f2 Q^2 with
@@ -205,25 +328,16 @@ struct ExpTol<double> {
 //   alpha' = gamma c0, beta' = alpha + gamma c1, gamma' = beta.
 // The series runs until the remainder bound rho^k/k! (rho = ||Q||_F) drops
 // below the working precision; for rho > 1 the argument is halved s times and
-// the result squared s times.
-template <class R>
+// the result squared s times.  ROWS = 2 returns rows 0 and 1 only (enough to
+// update a 12-real link), unless squarings are needed.
+template <class R, int ROWS = 3>
 __device__ __forceinline__ M3<R> su3_exp(const Alg<R> &X) {
     // Q = -i X
-    M3<R> Q;
-    Q.e[0][0] = {X.a[6], R(0)};
-    Q.e[1][1] = {X.a[7], R(0)};
-    Q.e[2][2] = {-(X.a[6] + X.a[7]), R(0)};
-    Q.e[0][1] = {X.a[1], -X.a[0]};
-    Q.e[0][2] = {X.a[3], -X.a[2]};
-    Q.e[1][2] = {X.a[5], -X.a[4]};
-    Q.e[1][0] = cconj(Q.e[0][1]);
-    Q.e[2][0] = cconj(Q.e[0][2]);
-    Q.e[2][1] = cconj(Q.e[1][2]);
-
-    R q00 = Q.e[0][0].x, q11 = Q.e[1][1].x, q22 = Q.e[2][2].x;
-    R n01 = Q.e[0][1].x * Q.e[0][1].x + Q.e[0][1].y * Q.e[0][1].y;
-    R n02 = Q.e[0][2].x * Q.e[0][2].x + Q.e[0][2].y * Q.e[0][2].y;
-    R n12 = Q.e[1][2].x * Q.e[1][2].x + Q.e[1][2].y * Q.e[1][2].y;
+    R q00 = X.a[6], q11 = X.a[7], q22 = -(X.a[6] + X.a[7]);
+    cx<R> q01 = {X.a[1], -X.a[0]}, q02 = {X.a[3], -X.a[2]}, q12 = {X.a[5], -X.a[4]};
+    R n01 = q01.x * q01.x + q01.y * q01.y;
+    R n02 = q02.x * q02.x + q02.y * q02.y;
+    R n12 = q12.x * q12.x + q12.y * q12.y;
     R fro2 = q00 * q00 + q11 * q11 + q22 * q22 + R(2) * (n01 + n02 + n12);
 
     int s = 0;
@@ -231,34 +345,32 @@ __device__ __forceinline__ M3<R> su3_exp(const Alg<R> &X) {
         // halve until ||Q||_F <= 1
         R f = fro2;
         while (f > R(1) && s < 30) { f *= R(0.25); s++; }
-        R sc = ldexp(R(1), -s);
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int j = 0; j < 3; j++) { Q.e[i][j].x *= sc; Q.e[i][j].y *= sc; }
+        const R sc = ldexp(R(1), -s), sc2 = sc * sc;
         q00 *= sc; q11 *= sc; q22 *= sc;
-        R sc2 = sc * sc;
+        q01 = {q01.x * sc, q01.y * sc};
+        q02 = {q02.x * sc, q02.y * sc};
+        q12 = {q12.x * sc, q12.y * sc};
         n01 *= sc2; n02 *= sc2; n12 *= sc2;
         fro2 *= sc2;
     }
-
-    R c1 = R(0.5) * fro2;
-    // det of a Hermitian 3x3: q00 q11 q22 + 2 Re(q01 q12 q20) - q00|q12|^2 - q11|q02|^2 - q22|q01|^2
-    cx<R> t = cmul(Q.e[0][1], Q.e[1][2]);
-    R re3 = t.x * Q.e[0][2].x + t.y * Q.e[0][2].y;  // Re(q01 q12 conj(q02))
-    R c0 = q00 * q11 * q22 + R(2) * re3 - q00 * n12 - q11 * n02 - q22 * n01;
+    const R c1 = R(0.5) * fro2;
+    // det of a Hermitian 3x3: q00 q11 q22 + 2 Re(q01 q12 conj(q02)) - q00|q12|^2 - q11|q02|^2 - q22|q01|^2
+    const cx<R> t = cmul(q01, q12);
+    const R re3 = t.x * q02.x + t.y * q02.y;
+    const R c0 = q00 * q11 * q22 + R(2) * re3 - q00 * n12 - q11 * n02 - q22 * n01;
 
     // series: term k holds alpha_k/k!, beta_k/k!, gamma_k/k!, weight i^k
     R al = R(1), be = R(0), ga = R(0);
     cx<R> f0 = {R(1), R(0)}, f1 = {R(0), R(0)}, f2 = {R(0), R(0)};
-    R rho = sqrt(fro2);
+    const R rho = sqrt(fro2);
     R bound = R(1);
+#pragma unroll
     for (int k = 1; k <= ExpTol<R>::kmax; k++) {
-        bound = bound * rho / R(k);
-        R inv = R(1) / R(k);
-        R nal = ga * c0 * inv;
-        R nbe = (al + ga * c1) * inv;
-        R nga = be * inv;
+        const R inv = (R)kInvK[k];
+        bound = bound * rho * inv;
+        const R nal = ga * c0 * inv;
+        const R nbe = (al + ga * c1) * inv;
+        const R nga = be * inv;
         al = nal; be = nbe; ga = nga;
         switch (k & 3) {
             case 0: f0.x += al; f1.x += be; f2.x += ga; break;
@@ -269,18 +381,37 @@ __device__ __forceinline__ M3<R> su3_exp(const Alg<R> &X) {
         if (bound < ExpTol<R>::tol) break;
     }
 
-    // Q^2 (Hermitian)
-    M3<R> Q2 = mul_nn(Q, Q);
+    // Q^2 (Hermitian): diagonal and upper triangle
+    const R s00 = q00 * q00 + n01 + n02;
+    const R s11 = q11 * q11 + n01 + n12;
+    const R s22 = q22 * q22 + n02 + n12;
+    // (Q^2)_01 = q00 q01 + q01 q11 + q02 conj(q12)
+    cx<R> s01 = {(q00 + q11) * q01.x, (q00 + q11) * q01.y};
+    s01 = cmadd_nc(s01, q02, q12);
+    // (Q^2)_02 = q00 q02 + q01 q12 + q02 q22
+    cx<R> s02 = {(q00 + q22) * q02.x, (q00 + q22) * q02.y};
+    s02 = cmadd(s02, q01, q12);
+    // (Q^2)_12 = conj(q01) q02 + q11 q12 + q12 q22
+    cx<R> s12 = {(q11 + q22) * q12.x, (q11 + q22) * q12.y};
+    s12 = cmadd_cn(s12, q01, q02);
+
+    // E = f0 + f1 Q + f2 Q^2
+    auto ent = [&](cx<R> q, cx<R> sq) { return cmadd(cmul(f1, q), f2, sq); };
+    auto dia = [&](R q, R sq) {
+        return cx<R>{f0.x + f1.x * q + f2.x * sq, f0.y + f1.y * q + f2.y * sq};
+    };
     M3<R> E;
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            cx<R> v = cmul(f1, Q.e[i][j]);
-            v = cmadd(v, f2, Q2.e[i][j]);
-            if (i == j) v = cadd(v, f0);
-            E.e[i][j] = v;
-        }
+    E.e[0][0] = dia(q00, s00);
+    E.e[0][1] = ent(q01, s01);
+    E.e[0][2] = ent(q02, s02);
+    E.e[1][0] = ent(cconj(q01), cconj(s01));
+    E.e[1][1] = dia(q11, s11);
+    E.e[1][2] = ent(q12, s12);
+    if (ROWS == 3 || s > 0) {
+        E.e[2][0] = ent(cconj(q02), cconj(s02));
+        E.e[2][1] = ent(cconj(q12), cconj(s12));
+        E.e[2][2] = dia(q22, s22);
+    }
     for (int i = 0; i < s; i++) E = mul_nn(E, E);
     return E;
 }

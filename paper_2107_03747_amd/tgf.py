@@ -92,6 +92,8 @@ class tgf_flow_params(ctypes.Structure):
 class tgf_timing(ctypes.Structure):
     _fields_ = [("stage_ms", ctypes.c_double), ("stage_launches", ctypes.c_int64),
                 ("stage_bytes", ctypes.c_double), ("stage_site_updates", ctypes.c_double),
+                ("aux_ms", ctypes.c_double), ("aux_launches", ctypes.c_int64),
+                ("aux_bytes", ctypes.c_double),
                 ("measure_ms", ctypes.c_double), ("measure_launches", ctypes.c_int64)]
 
 

@@ -48,8 +48,9 @@ def test_workspace_sizes_scale_with_storage():
     f64 = tgf.workspace_bytes(g, "f64")
     f32 = tgf.workspace_bytes(g, "f32")
     c12 = tgf.workspace_bytes(g, "f32c12")
-    # two link buffers + X: 2*4*9*16 + 4*4*16 bytes/site for FP64 ...
-    assert f64 - f32 == pytest.approx(V * (2 * 4 * 9 * 8 + 4 * 4 * 8), abs=4096)
+    # two link buffers + X + plaquette algebra: (2*4*9 + 4*4 + 6*4) complex/site,
+    # 16 bytes each in FP64, 8 in FP32
+    assert f64 - f32 == pytest.approx(V * (2 * 4 * 9 + 4 * 4 + 6 * 4) * 8, abs=4096)
     assert f32 - c12 == pytest.approx(V * (2 * 4 * 3 * 8), abs=4096)
 
 
