@@ -63,24 +63,68 @@ def n_steps(t_end, t0=0.0):
 
 
 # Algorithmic work per site per RK3 step (3 stages) -- see the design doc.
-def bytes_per_site_step(storage):
+def bytes_per_site_step(storage, variant="site"):
     ne, cb = (6, 8) if storage == "f32c12" else ((9, 8) if storage == "f32" else (9, 16))
     links = 3 * 2 * 4 * ne * cb           # read + write every stage
     x = (1 + 2 + 1) * 4 * 4 * cb          # X: write, read+write, read
-    return links + x
+    extra = 0
+    if variant.startswith("split"):       # A written + read, links read by both parts
+        extra = 3 * (2 * 6 * 4 * cb + 4 * ne * cb)
+    return links + x + extra
+
+
+MM = 198.0            # 3x3 complex product: 27 complex multiplies + 18 complex adds
+R2 = 132.0            # rows 0,1 of a 3x3 complex product
+REBUILD = 42.0        # row 2 = conj(row0 x row1): 6 complex multiplies + 3 subtractions
+EXP, XUPD = 300.0, 56.0
+
+
+def flops_per_site_stage(storage, variant, part=1):
+    """Real FP operations per site for one RK stage, by kernel."""
+    c12 = storage == "f32c12"
+    upd = R2 if c12 else MM
+    if variant.startswith("site"):
+        return 46 * MM + 4 * (EXP + upd + XUPD) + (REBUILD * 44 if c12 else 0)
+    if variant.startswith("link"):
+        return 4 * (13 * MM + EXP + upd + XUPD) + (REBUILD * 4 * 19 if c12 else 0)
+    if part == 0:     # six plaquettes as two-row products + 2.5 rebuilt entries + P_ah
+        return 6 * (3 * R2 + 35 + 16) + (REBUILD * 16 if c12 else 0)
+    # part 1: three conjugations U^+ A U (258) per link + exponential + update
+    return 4 * (3 * 258 + 24 + EXP + upd + XUPD) + (REBUILD * 16 if c12 else 0)
 
 
 def flops_per_site_step(storage, variant):
-    mm = 198.0                             # 3x3 complex product: 27 cmul + 18 cadd
-    if variant in ("site", "site_xcd"):
-        per_stage = 46 * mm                # 6 shared plaquettes (3 each) + 12 lower (2) + 4
-        loads = 4 + 12 + 36                # link loads per site (row-2 rebuilds for C12)
-    else:
-        per_stage = 52 * mm                # 4 links x (6 staples x 2 + 1)
-        loads = 4 * (1 + 6 * 3)
-    per_link = 40 + 16 + 300 + (2 * 3 * 3 * 8 - 12 if storage == "f32c12" else mm)
-    rebuild = 42 * loads if storage == "f32c12" else 0
-    return 3 * (per_stage + 4 * per_link + rebuild)
+    parts = (0, 1) if variant.startswith("split") else (1,)
+    return 3 * sum(flops_per_site_stage(storage, variant, p) for p in parts)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "su3_dev.h", "layout.h"):
+        with open(os.path.join(ROOT, "paper_2107_03747_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(variant, storage, workload):
+    """Counter-based HBM bytes per stage launch from profiles/*_hbm.md, when
+    that summary was taken on the current kernel sources, variant and workload."""
+    import glob
+    want = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm.md"))):
+        meta = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(("|", "#", " ", "`")):
+                    k, v = line.split(":", 1)
+                    meta[k.strip()] = v.strip()
+        if (meta.get("kernel-source-sha256-16") == want and meta.get("variant") == variant
+                and meta.get("storage", "f32c12") == storage
+                and meta.get("workload", "batch") == workload
+                and "traffic_bytes_per_launch" in meta):
+            return float(meta["traffic_bytes_per_launch"]), os.path.basename(path)
+    return None, None
 
 
 def make_inputs(cfgs, device):
@@ -161,6 +205,27 @@ def cpu_baseline(cfgs, inputs, gpu_rows, target_s=12.0):
     }, err, float(tt)
 
 
+def copy_mode(tgf, torch, args):
+    """Plain copy of a known size with the library's copy kernel: reads and
+    writes `bytes` each per launch.  Used to calibrate the HBM counters."""
+    nbytes = int(args.copy_gib * (1 << 30)) // 16 * 16
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.random_(0, 255)
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        tgf.stream_copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tgf.stream_copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"mode": "copy", "bytes_per_launch_read": nbytes,
+                      "bytes_per_launch_written": nbytes, "launches": args.steps,
+                      "ms_per_launch": round(dt * 1e3, 4),
+                      "copy_gbs": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +236,9 @@ def main():
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--mode", choices=("flow", "copy"), default="flow",
+                    help="copy: time the library's plain HBM copy kernel (counter calibration)")
+    ap.add_argument("--copy-gib", type=float, default=2.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -182,6 +250,10 @@ def main():
     import torch
 
     from paper_2107_03747_amd import tgf
+
+    if args.mode == "copy":
+        copy_mode(tgf, torch, args)
+        return
 
     cfgs = batch_workload() if args.workload == "batch" else large_workload()
     log(f"generating {len(cfgs)} configurations on the GPU")
@@ -201,35 +273,44 @@ def main():
     f.load_all(inputs)
     f.flow(EPS, [c[3] for c in cfgs], 0.1, 10, tgf.TGF_TIMING)
     tm = f.timing()
-    stage_avg_ms = tm["stage_ms"] / tm["stage_launches"]
-    gbs = tm["stage_bytes"] / (tm["stage_ms"] * 1e-3) / 1e9
-    su_per_s_kernel = tm["stage_site_updates"] / (tm["stage_ms"] * 1e-3)
-    fl = flops_per_site_step(args.storage, variant)
-    tflops = su_per_s_kernel * fl / 1e12
+    n_launch = tm["stage_launches"]
+    stage_avg_ms = tm["stage_ms"] / n_launch
+    bytes_per_launch = tm["stage_bytes"] / n_launch
+    site_stages_per_launch = 3 * tm["stage_site_updates"] / n_launch
+    flops_per_launch = site_stages_per_launch * flops_per_site_stage(args.storage, variant, 1)
+    gbs = bytes_per_launch / (stage_avg_ms * 1e-3) / 1e9
+    tflops = flops_per_launch / (stage_avg_ms * 1e-3) / 1e12
     hbm_frac = gbs / HBM_PEAK_GBS
     alu_frac = tflops / ALU_PEAK_TFLOPS
-    per_launch_bytes = tm["stage_bytes"] / tm["stage_launches"]
+    alu = alu_frac >= hbm_frac
+    traffic, traffic_src = profiled_traffic(variant, args.storage, args.workload)
+    kname = {"site": "stage_site_kernel", "link": "stage_link_kernel",
+             "split": "split_link_kernel"}[variant.split("_")[0]]
+    targ = "double, 9" if args.storage == "f64" else ("float, 6" if args.storage == "f32c12"
+                                                      else "float, 9")
     roofline = {
-        "kernel": f"stage_{'site' if 'site' in variant else 'link'}_kernel "
-                  f"<{'float' if args.storage != 'f64' else 'double'}, "
-                  f"{6 if args.storage == 'f32c12' else 9}>",
-        "bound": "alu" if alu_frac >= hbm_frac else "hbm",
-        "achieved": round(tflops if alu_frac >= hbm_frac else gbs, 3),
-        "peak": round(ALU_PEAK_TFLOPS, 1) if alu_frac >= hbm_frac else HBM_PEAK_GBS,
-        "unit": "TFLOP/s" if alu_frac >= hbm_frac else "GB/s",
-        "frac": round(max(alu_frac, hbm_frac), 4),
-        "traffic": None,
-        "hbm_gbs": round(gbs, 1),
-        "hbm_frac": round(hbm_frac, 4),
+        "kernel": f"{kname}<{targ}>",
+        "bound": "alu" if alu else "hbm",
+        "achieved": round(tflops if alu else gbs, 3),
+        "peak": round(ALU_PEAK_TFLOPS, 1) if alu else HBM_PEAK_GBS,
+        "unit": "TFLOP/s" if alu else "GB/s",
+        "frac": round(alu_frac if alu else hbm_frac, 4),
+        "traffic": traffic,
+        "traffic_source": traffic_src,
         "alu_tflops": round(tflops, 2),
         "alu_frac": round(alu_frac, 4),
+        "hbm_gbs_algorithmic": round(gbs, 1),
+        "hbm_frac": round(hbm_frac, 4),
         "avg_launch_ms": round(stage_avg_ms, 4),
-        "launches": int(tm["stage_launches"]),
-        "bytes_per_launch": round(per_launch_bytes),
-        "bytes_per_site_step": bytes_per_site_step(args.storage),
-        "flops_per_site_step": round(fl),
+        "launches": int(n_launch),
+        "bytes_per_launch": round(bytes_per_launch),
+        "flops_per_launch": round(flops_per_launch),
+        "bytes_per_site_step": bytes_per_site_step(args.storage, variant),
+        "flops_per_site_step": round(flops_per_site_step(args.storage, variant)),
+        "aux_kernel_ms_per_flow": round(tm["aux_ms"], 3),
         "measure_ms_per_flow": round(tm["measure_ms"], 3),
     }
+    whole_gbs = site_updates * bytes_per_site_step(args.storage, variant) / dt / 1e9
 
     out = {
         "metric": METRIC,
@@ -260,6 +341,8 @@ def main():
             "hip_graph": True,
         },
         "roofline": roofline,
+        "hbm_gbs_whole_pass": round(whole_gbs, 1),
+        "hbm_frac_whole_pass": round(whole_gbs / HBM_PEAK_GBS, 4),
     }
 
     if not args.no_fp64 and args.storage != "f64":
