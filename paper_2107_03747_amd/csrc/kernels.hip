@@ -70,32 +70,44 @@ __device__ __forceinline__ void st(gptr<v2<R>> q, size_t k, cx<R> z) {
 // geometry
 
 struct Geo {
-    int d[4];
-    int s[4];      // index strides
-    int n[4];      // coordinates of this site
-    int i;         // site index
+    // scalar members (no arrays), so a runtime direction index never turns
+    // the struct into addressable private or LDS memory
+    int d0, d1, d2, d3;
+    int s1, s2, s3;       // index strides (s0 = 1)
+    int n0, n1, n2, n3;   // coordinates of this site
+    int i;                // site index
+    __device__ __forceinline__ int d(int mu) const {
+        return mu == 0 ? d0 : (mu == 1 ? d1 : (mu == 2 ? d2 : d3));
+    }
+    __device__ __forceinline__ int s(int mu) const {
+        return mu == 0 ? 1 : (mu == 1 ? s1 : (mu == 2 ? s2 : s3));
+    }
+    __device__ __forceinline__ int n(int mu) const {
+        return mu == 0 ? n0 : (mu == 1 ? n1 : (mu == 2 ? n2 : n3));
+    }
     __device__ __forceinline__ int up(int mu) const {        // delta to n + mu
-        return n[mu] == d[mu] - 1 ? -(d[mu] - 1) * s[mu] : s[mu];
+        return n(mu) == d(mu) - 1 ? -(d(mu) - 1) * s(mu) : s(mu);
     }
     __device__ __forceinline__ int dn(int mu) const {        // delta to n - mu
-        return n[mu] == 0 ? (d[mu] - 1) * s[mu] : -s[mu];
+        return n(mu) == 0 ? (d(mu) - 1) * s(mu) : -s(mu);
+    }
+    __device__ __forceinline__ int back(int mu) const {      // coordinate n_mu - 1 (periodic)
+        return n(mu) == 0 ? d(mu) - 1 : n(mu) - 1;
     }
 };
 
 __device__ __forceinline__ Geo make_geo(const CfgDesc &c, int i) {
     Geo g;
     g.i = i;
-#pragma unroll
-    for (int m = 0; m < 4; m++) g.d[m] = c.d[m];
-    g.s[0] = 1;
-    g.s[1] = c.d[0];
-    g.s[2] = c.d[0] * c.d[1];
-    g.s[3] = g.s[2] * c.d[2];
+    g.d0 = c.d[0]; g.d1 = c.d[1]; g.d2 = c.d[2]; g.d3 = c.d[3];
+    g.s1 = c.d[0];
+    g.s2 = c.d[0] * c.d[1];
+    g.s3 = g.s2 * c.d[2];
     int r = i;
-    g.n[0] = r % c.d[0]; r /= c.d[0];
-    g.n[1] = r % c.d[1]; r /= c.d[1];
-    g.n[2] = r % c.d[2];
-    g.n[3] = r / c.d[2];
+    g.n0 = r % c.d[0]; r /= c.d[0];
+    g.n1 = r % c.d[1]; r /= c.d[1];
+    g.n2 = r % c.d[2];
+    g.n3 = r / c.d[2];
     return g;
 }
 
@@ -238,12 +250,15 @@ __device__ __forceinline__ void reunitarise(M3<R> &U) {
 template <class R, int NE>
 __device__ __forceinline__ M3<R> upper_plaq(const Links<R, NE> &W, const CfgDesc &c,
                                             const Geo &g, int mu, int nu) {
-    M3<R> A = mul_nn(W(mu, g.i), W(nu, g.i + g.up(mu)));
-    A = mul_nd(A, W(mu, g.i + g.up(nu)));
-    A = mul_nd(A, W(nu, g.i));
+    // P is in SU(3): rows 0,1 by two-row products, row 2 = conj(row0 x row1)
+    R2<R> A = r2_of(W(mu, g.i));
+    A = r2_mul_nn(A, W(nu, g.i + g.up(mu)));
+    A = r2_mul_nd(A, W(mu, g.i + g.up(nu)));
+    A = r2_mul_nd(A, W(nu, g.i));
+    M3<R> P = r2_full(A);
     int k = twist_exp(c, mu, nu);
-    if (k && g.n[mu] == 0 && g.n[nu] == 0) m_scale(A, cconj(omega_pow<R>(k)));
-    return A;
+    if (k && g.n(mu) == 0 && g.n(nu) == 0) m_scale(P, cconj(omega_pow<R>(k)));
+    return P;
 }
 
 // Upper staple U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+ times Z^*_{mu nu}(n).
@@ -253,7 +268,7 @@ __device__ __forceinline__ M3<R> upper_staple(const Links<R, NE> &W, const CfgDe
     M3<R> A = mul_nd(W(nu, g.i + g.up(mu)), W(mu, g.i + g.up(nu)));
     A = mul_nd(A, W(nu, g.i));
     int k = twist_exp(c, mu, nu);
-    if (k && g.n[mu] == 0 && g.n[nu] == 0) m_scale(A, cconj(omega_pow<R>(k)));
+    if (k && g.n(mu) == 0 && g.n(nu) == 0) m_scale(A, cconj(omega_pow<R>(k)));
     return A;
 }
 
@@ -267,9 +282,22 @@ __device__ __forceinline__ M3<R> lower_staple(const Links<R, NE> &W, const CfgDe
     M3<R> T = mul_nn(W(mu, imn), W(nu, imn + g.up(mu)));
     M3<R> L = mul_dn(T, W(nu, imn));
     int k = twist_exp(c, mu, nu);
-    int nnu = g.n[nu] == 0 ? g.d[nu] - 1 : g.n[nu] - 1;
-    if (k && g.n[mu] == 0 && nnu == 0) m_scale(L, omega_pow<R>(k));
+    int nnu = g.back(nu);
+    if (k && g.n(mu) == 0 && nnu == 0) m_scale(L, omega_pow<R>(k));
     return L;
+}
+
+// S += Z_{mu nu}(n-nu) U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu), accumulated in
+// place; the twist factor is folded into T = U_mu(n-nu) U_nu(n+mu-nu) as
+// z T^+ U = (conj(z) T)^+ U, so twisted and untwisted lanes run the same code.
+template <class R, int NE>
+__device__ __forceinline__ void acc_lower_staple(M3<R> &S, const Links<R, NE> &W,
+                                                 const CfgDesc &c, const Geo &g, int mu, int nu) {
+    const int imn = g.i + g.dn(nu);
+    M3<R> T = mul_nn(W(mu, imn), W(nu, imn + g.up(mu)));
+    const int k = twist_exp(c, mu, nu);
+    if (k && g.n(mu) == 0 && g.back(nu) == 0) m_scale(T, cconj(omega_pow<R>(k)));
+    m_acc_mul_dn(S, T, W(nu, imn));
 }
 
 // RK stage tail for one link: X = B eps F + A X_old; W_out = exp(X) W_in.
@@ -334,6 +362,23 @@ __device__ __forceinline__ int remap_block(int b, int nb, int xcd) {
     return (b & 7) * per + (b >> 3);
 }
 
+// Lower staples of link MU summed, Omega_MU += U_MU(n) S, then the RK update
+// (MU is a template argument so that acc[] is never indexed at run time).
+template <class R, int NE, int MU>
+__device__ __forceinline__ void site_lower_update(const Links<R, NE> &W, gptr<v2<R>> Wout,
+                                                  gptr<v2<R>> X, const CfgDesc &c, const Geo &g,
+                                                  M3<R> &om, R beps, R ac, const StageArgs &a) {
+    M3<R> S;
+    m_zero(S);
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == MU) continue;
+        acc_lower_staple(S, W, c, g, MU, nu);
+    }
+    m_acc_mul_nn(om, W(MU, g.i), S);
+    update_link<R, NE>(W, Wout, X, c.stride, MU, g.i, om, beps, ac, a.stage, a.reunit);
+}
+
 // One thread per site: the six upper plaquettes feed both of their links
 // (P_{nu mu} = P_{mu nu}^+), the twelve lower staples are summed per link
 // before the single U_mu(n) S product.
@@ -369,19 +414,10 @@ __global__ __launch_bounds__(256) void stage_site_kernel(StageArgs a) {
             m_acc(acc[mu], P);
             m_acc_scaled_dag(acc[nu], cx<R>{R(1), R(0)}, P);
         }
-#pragma unroll
-    for (int mu = 0; mu < 4; mu++) {
-        M3<R> S;
-        m_zero(S);
-#pragma unroll
-        for (int nu = 0; nu < 4; nu++) {
-            if (nu == mu) continue;
-            m_acc(S, lower_staple(W, c, g, mu, nu));
-        }
-        M3<R> US = mul_nn(W(mu, i), S);
-        m_acc(acc[mu], US);
-        update_link<R, NE>(W, Wout, X, c.stride, mu, i, acc[mu], beps, ac, a.stage, a.reunit);
-    }
+    site_lower_update<R, NE, 0>(W, Wout, X, c, g, acc[0], beps, ac, a);
+    site_lower_update<R, NE, 1>(W, Wout, X, c, g, acc[1], beps, ac, a);
+    site_lower_update<R, NE, 2>(W, Wout, X, c, g, acc[2], beps, ac, a);
+    site_lower_update<R, NE, 3>(W, Wout, X, c, g, acc[3], beps, ac, a);
 }
 
 // One thread per link: a work-group is one tile of 64 sites x 4 directions,
@@ -438,14 +474,6 @@ __global__ __launch_bounds__(256) void stage_link_kernel(StageArgs a) {
 // once per lattice instead of up to four times); part 1 forms the force of
 // every link from three own and three neighbouring A and updates the link.
 
-template <class R>
-__device__ __forceinline__ void r2_scale(R2<R> &A, cx<R> z) {
-#pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) A.e[i][j] = cmul(z, A.e[i][j]);
-}
-
 template <class R, int NE>
 __global__ __launch_bounds__(256) void plaq_alg_kernel(StageArgs a) {
     const int nb = (a.n_tiles + 3) >> 2;
@@ -472,7 +500,7 @@ __global__ __launch_bounds__(256) void plaq_alg_kernel(StageArgs a) {
             P = r2_mul_nd(P, W(mu, i + g.up(nu)));
             P = r2_mul_nd(P, W(nu, i));
             const int k = c.tw[p];
-            if (k && g.n[mu] == 0 && g.n[nu] == 0) r2_scale(P, cconj(omega_pow<R>(k)));
+            if (k && g.n(mu) == 0 && g.n(nu) == 0) r2_scale(P, cconj(omega_pow<R>(k)));
             R A8[8];
             r2_proj_ah(P, R(1), A8);
             gptr<v2<R>> q = Ap + (size_t)(p * 4) * c.stride;
@@ -603,6 +631,29 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// rows 0,1 of U^+
+template <class R>
+__device__ __forceinline__ R2<R> r2_dag(const M3<R> &U) {
+    R2<R> r;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) r.e[i][j] = cconj(U.e[j][i]);
+    return r;
+}
+
+// C += z L for a leaf L in SU(3) given by rows 0,1 (row 2 = conj(row0 x row1));
+// returns Re Tr(z L).
+template <class R>
+__device__ __forceinline__ R acc_leaf(M3<R> &C, R2<R> L, bool twisted, cx<R> z) {
+    if (twisted) r2_scale(L, z);   // z in Z_3: z L is again in SU(3)
+    M3<R> F = r2_full(L);
+    m_acc(C, F);
+    return F.e[0][0].x + F.e[1][1].x + F.e[2][2].x;
+}
+
+// Clover G_{mu nu}(n) of eq. gmunu: -(i/8)(C - C^+), C the four leaves, each
+// with Z^*_{mu nu} of its base site; also returns Re Tr of leaf 1 (the plaquette).
 template <class R, int NE>
 __device__ __forceinline__ Herm<R> clover_G(const Links<R, NE> &W, const CfgDesc &c, const Geo &g,
                                             int mu, int nu, R &retr_plaq) {
@@ -610,37 +661,36 @@ __device__ __forceinline__ Herm<R> clover_G(const Links<R, NE> &W, const CfgDesc
     const int i_m = i + g.dn(mu), i_n = i + g.dn(nu);
     const int i_mn = i_m + g.dn(nu);
     const int k = twist_exp(c, mu, nu);
-    const int nm = g.n[mu] == 0 ? g.d[mu] - 1 : g.n[mu] - 1;
-    const int nn = g.n[nu] == 0 ? g.d[nu] - 1 : g.n[nu] - 1;
+    const int nm = g.back(mu);
+    const int nn = g.back(nu);
     const cx<R> zs = cconj(omega_pow<R>(k));
-    M3<R> C, L;
+    M3<R> C;
+    m_zero(C);
+    R2<R> L;
     // leaf 1: Z^*(n) U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
-    L = mul_nn(W(mu, i), W(nu, i + g.up(mu)));
-    L = mul_nd(L, W(mu, i + g.up(nu)));
-    L = mul_nd(L, W(nu, i));
-    if (k && g.n[mu] == 0 && g.n[nu] == 0) m_scale(L, zs);
-    retr_plaq = L.e[0][0].x + L.e[1][1].x + L.e[2][2].x;
-    C = L;
+    L = r2_of(W(mu, i));
+    L = r2_mul_nn(L, W(nu, i + g.up(mu)));
+    L = r2_mul_nd(L, W(mu, i + g.up(nu)));
+    L = r2_mul_nd(L, W(nu, i));
+    retr_plaq = acc_leaf(C, L, k && g.n(mu) == 0 && g.n(nu) == 0, zs);
     // leaf 2: Z^*(n-nu) U_nu(n-nu)^+ U_mu(n-nu) U_nu(n-nu+mu) U_mu(n)^+
-    L = mul_dn(W(nu, i_n), W(mu, i_n));
-    L = mul_nn(L, W(nu, i_n + g.up(mu)));
-    L = mul_nd(L, W(mu, i));
-    if (k && g.n[mu] == 0 && nn == 0) m_scale(L, zs);
-    m_acc(C, L);
+    L = r2_dag(W(nu, i_n));
+    L = r2_mul_nn(L, W(mu, i_n));
+    L = r2_mul_nn(L, W(nu, i_n + g.up(mu)));
+    L = r2_mul_nd(L, W(mu, i));
+    acc_leaf(C, L, k && g.n(mu) == 0 && nn == 0, zs);
     // leaf 3: Z^*(n-mu) U_nu(n) U_mu(n-mu+nu)^+ U_nu(n-mu)^+ U_mu(n-mu)
-    L = mul_nd(W(nu, i), W(mu, i_m + g.up(nu)));
-    L = mul_nd(L, W(nu, i_m));
-    L = mul_nn(L, W(mu, i_m));
-    if (k && nm == 0 && g.n[nu] == 0) m_scale(L, zs);
-    m_acc(C, L);
+    L = r2_of(W(nu, i));
+    L = r2_mul_nd(L, W(mu, i_m + g.up(nu)));
+    L = r2_mul_nd(L, W(nu, i_m));
+    L = r2_mul_nn(L, W(mu, i_m));
+    acc_leaf(C, L, k && nm == 0 && g.n(nu) == 0, zs);
     // leaf 4: Z^*(n-mu-nu) U_mu(n-mu)^+ U_nu(n-mu-nu)^+ U_mu(n-mu-nu) U_nu(n-nu)
-    {
-        M3<R> A = mul_nn(W(nu, i_mn), W(mu, i_m));   // (U_mu(n-mu)^+ U_nu(n-mu-nu)^+)^+
-        L = mul_dn(A, W(mu, i_mn));
-        L = mul_nn(L, W(nu, i_n));
-    }
-    if (k && nm == 0 && nn == 0) m_scale(L, zs);
-    m_acc(C, L);
+    L = r2_dag(W(mu, i_m));
+    L = r2_mul_nd(L, W(nu, i_mn));
+    L = r2_mul_nn(L, W(mu, i_mn));
+    L = r2_mul_nn(L, W(nu, i_n));
+    acc_leaf(C, L, k && nm == 0 && nn == 0, zs);
     // G = -(i/8)(C - C^+)
     Herm<R> G;
     const R q = R(0.125);
@@ -657,49 +707,55 @@ __device__ __forceinline__ Herm<R> clover_G(const Links<R, NE> &W, const CfgDesc
     return G;
 }
 
+// Measurement: a work-group is one tile of 64 sites x the three dual plane
+// pairs (01,23), (02,13), (03,12); wave w computes the two clovers of pair w,
+// their e(n), plaquette and action densities and the pair's term of
+// q(n) = (1/4 pi^2)[Tr G01 G23 - Tr G02 G13 + Tr G03 G12], reduced in FP64
+// over the wave into partials[tile][pair][4].
+template <class R, int NE, int PAIR>
+__device__ __forceinline__ void measure_pair(const Links<R, NE> &W, const CfgDesc &c, const Geo &g,
+                                             double out[4]) {
+    constexpr int a0 = 0, a1 = PAIR + 1;                       // (0,1) (0,2) (0,3)
+    constexpr int b0 = PAIR == 0 ? 2 : 1;
+    constexpr int b1 = PAIR == 2 ? 2 : 3;                      // (2,3) (1,3) (1,2)
+    R p1, p2;
+    Herm<R> Ga = clover_G(W, c, g, a0, a1, p1);
+    Herm<R> Gb = clover_G(W, c, g, b0, b1, p2);
+    const R x = tr_herm2(Ga, Gb);
+    out[0] = (double)(tr_herm2(Ga, Ga) + tr_herm2(Gb, Gb));
+    out[1] = (double)(PAIR == 1 ? -x : x) * (1.0 / (4.0 * M_PI * M_PI));
+    out[2] = (double)(p1 + p2);
+    out[3] = (double)((R(3) - p1) + (R(3) - p2));
+}
+
 template <class R, int NE>
-__global__ __launch_bounds__(256) void measure_kernel(const CfgDesc *__restrict__ cfgs,
+__global__ __launch_bounds__(192) void measure_kernel(const CfgDesc *__restrict__ cfgs,
                                                       const int *__restrict__ tile_start, int n_cfg,
                                                       int n_tiles, const MeasSlot *__restrict__ slots,
                                                       double *__restrict__ partials, int buf_sel) {
-    const int tile = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = blockIdx.x;
     if (tile >= n_tiles) return;
+    const int pair = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ci = find_cfg(tile_start, n_cfg, tile);
     if (slots[ci].row < 0) return;
     const CfgDesc c = cfgs[ci];
     const int i = (tile - tile_start[ci]) * kTile + (threadIdx.x & 63);
-    double e = 0, q = 0, p = 0, s = 0;
+    double v[4] = {0, 0, 0, 0};
     if (i < c.V) {
         const int sel = buf_sel < 0 ? c.cur : ((c.cur + buf_sel) & 1);
         const Links<R, NE> W{as_global<R>((const void *)(sel ? c.W[1] : c.W[0])), c.stride};
         const Geo g = make_geo(c, i);
-        // planes in dual pairs: (01,23), (02,13), (03,12); q picks up
-        // Tr G01 G23 - Tr G02 G13 + Tr G03 G12
-        R er = 0, pr = 0, sr = 0, qr = 0;
-        const int pa[3][2] = {{0, 1}, {0, 2}, {0, 3}}, pb[3][2] = {{2, 3}, {1, 3}, {1, 2}};
-#pragma unroll
-        for (int t = 0; t < 3; t++) {
-            R p1, p2;
-            Herm<R> Ga = clover_G(W, c, g, pa[t][0], pa[t][1], p1);
-            Herm<R> Gb = clover_G(W, c, g, pb[t][0], pb[t][1], p2);
-            er += tr_herm2(Ga, Ga) + tr_herm2(Gb, Gb);
-            pr += p1 + p2;
-            sr += (R(3) - p1) + (R(3) - p2);
-            R x = tr_herm2(Ga, Gb);
-            qr += (t == 1) ? -x : x;
+        switch (pair) {
+            case 0: measure_pair<R, NE, 0>(W, c, g, v); break;
+            case 1: measure_pair<R, NE, 1>(W, c, g, v); break;
+            default: measure_pair<R, NE, 2>(W, c, g, v); break;
         }
-        e = (double)er;
-        q = (double)qr * (1.0 / (4.0 * M_PI * M_PI));
-        p = (double)pr;
-        s = (double)sr;
     }
-    e = wave_sum(e);
-    q = wave_sum(q);
-    p = wave_sum(p);
-    s = wave_sum(s);
+#pragma unroll
+    for (int k = 0; k < 4; k++) v[k] = wave_sum(v[k]);
     if ((threadIdx.x & 63) == 0) {
-        double *o = partials + (size_t)tile * 4;
-        o[0] = e; o[1] = q; o[2] = p; o[3] = s;
+        double *o = partials + ((size_t)tile * 3 + pair) * 4;
+        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
     }
 }
 
@@ -714,7 +770,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const CfgDesc *__restrict
     const MeasSlot sl = slots[ci];
     if (sl.row < 0) return;
     const CfgDesc &c = cfgs[ci];
-    const int t0 = tile_start[ci], t1 = tile_start[ci + 1];
+    const int t0 = tile_start[ci] * 3, t1 = tile_start[ci + 1] * 3;   // (tile, pair) slots
     double acc[4] = {0, 0, 0, 0};
     for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
 #pragma unroll
@@ -928,15 +984,15 @@ hipError_t launch_measure(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
                           const int *tile_start, int n_cfg, int n_tiles, const MeasSlot *slots,
                           double *partials, int buf_sel) {
     if (n_tiles <= 0) return hipSuccess;
-    dim3 grid((n_tiles + 3) / 4);
+    dim3 grid(n_tiles);
     if (p == P_F64)
-        hipLaunchKernelGGL((measure_kernel<double, 9>), grid, dim3(256), 0, s, cfgs, tile_start,
+        hipLaunchKernelGGL((measure_kernel<double, 9>), grid, dim3(192), 0, s, cfgs, tile_start,
                            n_cfg, n_tiles, slots, partials, buf_sel);
     else if (c12)
-        hipLaunchKernelGGL((measure_kernel<float, 6>), grid, dim3(256), 0, s, cfgs, tile_start,
+        hipLaunchKernelGGL((measure_kernel<float, 6>), grid, dim3(192), 0, s, cfgs, tile_start,
                            n_cfg, n_tiles, slots, partials, buf_sel);
     else
-        hipLaunchKernelGGL((measure_kernel<float, 9>), grid, dim3(256), 0, s, cfgs, tile_start,
+        hipLaunchKernelGGL((measure_kernel<float, 9>), grid, dim3(192), 0, s, cfgs, tile_start,
                            n_cfg, n_tiles, slots, partials, buf_sel);
     return hipGetLastError();
 }

@@ -106,7 +106,8 @@ Layout make_layout(int32_t n_cfg, const tgf_geom *g, tgf_storage st) {
     L.off_tiles = o;    o = align_up(o + sizeof(int) * (n_cfg + 1), 256);
     L.off_flag = o;     o = align_up(o + 64, 256);
     L.off_check = o;    o = align_up(o + 64, 256);
-    size_t partial_doubles = std::max<size_t>((size_t)tiles * 4, 2 * (size_t)tiles);
+    // measurement: 4 doubles per (tile, plane pair); unitarity check: 2 per tile
+    size_t partial_doubles = (size_t)tiles * 3 * 4;
     L.off_partials = o; o = align_up(o + sizeof(double) * partial_doubles, 256);
     L.off_rows = o;     o = align_up(o + sizeof(double) * 6 * (size_t)kMaxRows * n_cfg, 256);
     L.off_meas = o;     o = align_up(o + sizeof(MeasSlot) * (size_t)(kMaxRows + 1) * n_cfg, 256);

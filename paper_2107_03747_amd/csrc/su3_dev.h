@@ -128,6 +128,36 @@ __device__ __forceinline__ void m_acc_scaled(M3<R> &acc, cx<R> z, const M3<R> &A
         for (int j = 0; j < 3; j++) acc.e[i][j] = cmadd(acc.e[i][j], z, A.e[i][j]);
 }
 
+// acc += A^+ B  (the product accumulated straight into acc)
+template <class R>
+__device__ __forceinline__ void m_acc_mul_dn(M3<R> &acc, const M3<R> &A, const M3<R> &B) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            cx<R> s = acc.e[i][j];
+            s = cmadd_cn(s, A.e[0][i], B.e[0][j]);
+            s = cmadd_cn(s, A.e[1][i], B.e[1][j]);
+            s = cmadd_cn(s, A.e[2][i], B.e[2][j]);
+            acc.e[i][j] = s;
+        }
+}
+
+// acc += A B
+template <class R>
+__device__ __forceinline__ void m_acc_mul_nn(M3<R> &acc, const M3<R> &A, const M3<R> &B) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            cx<R> s = acc.e[i][j];
+            s = cmadd(s, A.e[i][0], B.e[0][j]);
+            s = cmadd(s, A.e[i][1], B.e[1][j]);
+            s = cmadd(s, A.e[i][2], B.e[2][j]);
+            acc.e[i][j] = s;
+        }
+}
+
 // acc += A
 template <class R>
 __device__ __forceinline__ void m_acc(M3<R> &acc, const M3<R> &A) {
@@ -225,6 +255,26 @@ __device__ __forceinline__ R2<R> r2_mul_nd(const R2<R> &A, const M3<R> &B) {
             C.e[i][j] = s;
         }
     return C;
+}
+
+template <class R>
+__device__ __forceinline__ void r2_scale(R2<R> &A, cx<R> z) {
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) A.e[i][j] = cmul(z, A.e[i][j]);
+}
+
+// full SU(3) matrix from rows 0,1
+template <class R>
+__device__ __forceinline__ M3<R> r2_full(const R2<R> &A) {
+    M3<R> U;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) U.e[i][j] = A.e[i][j];
+    rebuild_row2(U);
+    return U;
 }
 
 template <class R>
