@@ -48,22 +48,30 @@ template <class R>
 __device__ __forceinline__ gptr<const v2<R>> as_global(const void *p) {
     return (gptr<const v2<R>>)p;
 }
+// Element k of an entry plane: `plane` is uniform (one SGPR pair), the lane
+// part is a 32-bit byte offset, so the access is a single global_load/store
+// with an SGPR base and a VGPR offset (sites per configuration are capped so
+// that every offset fits in 32 bits).
 template <class R>
-__device__ __forceinline__ cx<R> ld(gptr<const v2<R>> q, size_t k) {
-    v2<R> v = q[k];
+__device__ __forceinline__ unsigned lane_off(int i) {
+    return (unsigned)i * (unsigned)sizeof(v2<R>);
+}
+template <class R>
+__device__ __forceinline__ cx<R> ld(gptr<const v2<R>> plane, unsigned off) {
+    const v2<R> v = *(gptr<const v2<R>>)((gptr<const char>)plane + off);
     return {v.x, v.y};
 }
 template <class R>
-__device__ __forceinline__ cx<R> ld(gptr<v2<R>> q, size_t k) {
-    v2<R> v = q[k];
+__device__ __forceinline__ cx<R> ld(gptr<v2<R>> plane, unsigned off) {
+    const v2<R> v = *(gptr<const v2<R>>)((gptr<const char>)plane + off);
     return {v.x, v.y};
 }
 template <class R>
-__device__ __forceinline__ void st(gptr<v2<R>> q, size_t k, cx<R> z) {
+__device__ __forceinline__ void st(gptr<v2<R>> plane, unsigned off, cx<R> z) {
     v2<R> v;
     v.x = z.x;
     v.y = z.y;
-    q[k] = v;
+    *(gptr<v2<R>>)((gptr<char>)plane + off) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -160,18 +168,18 @@ struct Links {
     __device__ __forceinline__ M3<R> operator()(int mu, int i) const {
         // entry planes are uniform bases, the site index the lane offset
         gptr<const v2<R>> q = p + (size_t)(mu * NE) * stride;
-        const unsigned u = (unsigned)i;
+        const unsigned u = lane_off<R>(i);
         M3<R> U;
         U.e[0][0] = ld(q, u);
-        U.e[0][1] = ld(q, (size_t)stride + u);
-        U.e[0][2] = ld(q, (size_t)2 * stride + u);
-        U.e[1][0] = ld(q, (size_t)3 * stride + u);
-        U.e[1][1] = ld(q, (size_t)4 * stride + u);
-        U.e[1][2] = ld(q, (size_t)5 * stride + u);
+        U.e[0][1] = ld(q + (size_t)stride, u);
+        U.e[0][2] = ld(q + (size_t)2 * stride, u);
+        U.e[1][0] = ld(q + (size_t)3 * stride, u);
+        U.e[1][1] = ld(q + (size_t)4 * stride, u);
+        U.e[1][2] = ld(q + (size_t)5 * stride, u);
         if constexpr (NE == 9) {
-            U.e[2][0] = ld(q, (size_t)6 * stride + u);
-            U.e[2][1] = ld(q, (size_t)7 * stride + u);
-            U.e[2][2] = ld(q, (size_t)8 * stride + u);
+            U.e[2][0] = ld(q + (size_t)6 * stride, u);
+            U.e[2][1] = ld(q + (size_t)7 * stride, u);
+            U.e[2][2] = ld(q + (size_t)8 * stride, u);
         } else {
             rebuild_row2(U);
         }
@@ -183,17 +191,17 @@ template <class R, int NE>
 __device__ __forceinline__ void store_link(gptr<v2<R>> p, int stride, int mu, int i,
                                            const M3<R> &U) {
     gptr<v2<R>> q = p + (size_t)(mu * NE) * stride;
-    const unsigned u = (unsigned)i;
+    const unsigned u = lane_off<R>(i);
     st(q, u, U.e[0][0]);
-    st(q, (size_t)stride + u, U.e[0][1]);
-    st(q, (size_t)2 * stride + u, U.e[0][2]);
-    st(q, (size_t)3 * stride + u, U.e[1][0]);
-    st(q, (size_t)4 * stride + u, U.e[1][1]);
-    st(q, (size_t)5 * stride + u, U.e[1][2]);
+    st(q + (size_t)stride, u, U.e[0][1]);
+    st(q + (size_t)2 * stride, u, U.e[0][2]);
+    st(q + (size_t)3 * stride, u, U.e[1][0]);
+    st(q + (size_t)4 * stride, u, U.e[1][1]);
+    st(q + (size_t)5 * stride, u, U.e[1][2]);
     if constexpr (NE == 9) {
-        st(q, (size_t)6 * stride + u, U.e[2][0]);
-        st(q, (size_t)7 * stride + u, U.e[2][1]);
-        st(q, (size_t)8 * stride + u, U.e[2][2]);
+        st(q + (size_t)6 * stride, u, U.e[2][0]);
+        st(q + (size_t)7 * stride, u, U.e[2][1]);
+        st(q + (size_t)8 * stride, u, U.e[2][2]);
     }
 }
 
@@ -308,18 +316,18 @@ __device__ __forceinline__ void update_link(const Links<R, NE> &W, gptr<v2<R>> W
                                             int reunit) {
     Alg<R> Z = proj_ah(Omega, -beps);
     gptr<v2<R>> xp = X + (size_t)(mu * 4) * stride;
-    const unsigned u = (unsigned)i;
+    const unsigned u = lane_off<R>(i);
     if (stage > 0) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            cx<R> o = ld(xp, (size_t)k * stride + u);
+            cx<R> o = ld(xp + (size_t)k * stride, u);
             Z.a[2 * k] = fma(a, o.x, Z.a[2 * k]);
             Z.a[2 * k + 1] = fma(a, o.y, Z.a[2 * k + 1]);
         }
     }
     if (stage < 2) {
 #pragma unroll
-        for (int k = 0; k < 4; k++) st(xp, (size_t)k * stride + u, cx<R>{Z.a[2 * k], Z.a[2 * k + 1]});
+        for (int k = 0; k < 4; k++) st(xp + (size_t)k * stride, u, cx<R>{Z.a[2 * k], Z.a[2 * k + 1]});
     }
     M3<R> E = su3_exp<R, NE == 9 ? 3 : 2>(Z);
     M3<R> U = W(mu, i);
@@ -489,7 +497,7 @@ __global__ __launch_bounds__(256) void plaq_alg_kernel(StageArgs a) {
     const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
     gptr<v2<R>> Ap = as_global<R>(c.A);
     const Geo g = make_geo(c, i);
-    const unsigned u = (unsigned)i;
+    const unsigned u = lane_off<R>(i);
 #pragma unroll
     for (int mu = 0, p = 0; mu < 4; mu++)
 #pragma unroll
@@ -505,17 +513,17 @@ __global__ __launch_bounds__(256) void plaq_alg_kernel(StageArgs a) {
             r2_proj_ah(P, R(1), A8);
             gptr<v2<R>> q = Ap + (size_t)(p * 4) * c.stride;
 #pragma unroll
-            for (int t = 0; t < 4; t++) st(q, (size_t)t * c.stride + u, cx<R>{A8[2 * t], A8[2 * t + 1]});
+            for (int t = 0; t < 4; t++) st(q + (size_t)t * c.stride, u, cx<R>{A8[2 * t], A8[2 * t + 1]});
         }
 }
 
 template <class R>
 __device__ __forceinline__ void load_alg(gptr<const v2<R>> Ap, int stride, int p, int i, R out[8]) {
     gptr<const v2<R>> q = Ap + (size_t)(p * 4) * stride;
-    const unsigned u = (unsigned)i;
+    const unsigned u = lane_off<R>(i);
 #pragma unroll
     for (int t = 0; t < 4; t++) {
-        cx<R> v = ld(q, (size_t)t * stride + u);
+        cx<R> v = ld(q + (size_t)t * stride, u);
         out[2 * t] = v.x;
         out[2 * t + 1] = v.y;
     }
@@ -554,18 +562,18 @@ __device__ __forceinline__ void split_body(const StageArgs &a, const CfgDesc &c,
 #pragma unroll
     for (int t = 0; t < 8; t++) Z.a[t] = -beps * om[t];
     gptr<v2<R>> xp = X + (size_t)(MU * 4) * c.stride;
-    const unsigned u = (unsigned)i;
+    const unsigned u = lane_off<R>(i);
     if (a.stage > 0) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            cx<R> o = ld(xp, (size_t)k * c.stride + u);
+            cx<R> o = ld(xp + (size_t)k * c.stride, u);
             Z.a[2 * k] = fma(ac, o.x, Z.a[2 * k]);
             Z.a[2 * k + 1] = fma(ac, o.y, Z.a[2 * k + 1]);
         }
     }
     if (a.stage < 2) {
 #pragma unroll
-        for (int k = 0; k < 4; k++) st(xp, (size_t)k * c.stride + u, cx<R>{Z.a[2 * k], Z.a[2 * k + 1]});
+        for (int k = 0; k < 4; k++) st(xp + (size_t)k * c.stride, u, cx<R>{Z.a[2 * k], Z.a[2 * k + 1]});
     }
     const M3<R> E = su3_exp<R, NE == 9 ? 3 : 2>(Z);
     const M3<R> U = W(MU, i);

@@ -77,7 +77,8 @@ tgf_status validate_geoms(int32_t n_cfg, const tgf_geom *g) {
                 return fail(TGF_E_INVAL, "config " + std::to_string(c) + ": dims must be >= 2");
             V *= g[c].dims[m];
         }
-        if (V > (1LL << 30))
+        // every per-lane byte offset into an entry plane must fit in 32 bits
+        if (V > (1LL << 28) - 256)
             return fail(TGF_E_INVAL, "config " + std::to_string(c) + ": lattice too large");
         for (int k = 0; k < 6; k++)
             if (g[c].twist[k] < 0 || g[c].twist[k] > 2)
