@@ -1,0 +1,62 @@
+"""The pins of tests/test_oracle_pins.py must catch plausible mistakes.
+
+Each case plants one mistake in a scratch copy of the oracle's C source (a
+twist factor conjugated or moved, a leaf mis-oriented, an RK3 coefficient, a
+normalisation, a sign, a neighbour index, the schedule), rebuilds it, and
+requires the pin suite to fail.  CPU only; the real oracle is untouched.
+"""
+
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = [
+    ("lower staple factor conjugated",
+     "om = m_add(om, m_scale(zfac(L, imn, mu, nu), lo));",
+     "om = m_add(om, m_scale(conj(zfac(L, imn, mu, nu)), lo));"),
+    ("upper factor not conjugated",
+     "om = m_add(om, m_scale(conj(zfac(L, i, mu, nu)), up));",
+     "om = m_add(om, m_scale(zfac(L, i, mu, nu), up));"),
+    ("RK3 17/36 -> 17/9", "m_scale(-17.0 / 36.0, Z0[l])", "m_scale(-17.0 / 9.0, Z0[l])"),
+    ("RK3 3/4 -> 1/4", "m_scale(0.75, Z2[l])", "m_scale(0.25, Z2[l])"),
+    ("clover 1/8 -> 1/4", "(-I / 8.0)", "(-I / 4.0)"),
+    ("leaf 3 twist base n-nu",
+     "C = m_add(C, m_scale(conj(zfac(L, i_m, mu, nu)), plaq_s(L, links, i, pn, mm)));",
+     "C = m_add(C, m_scale(conj(zfac(L, i_n, mu, nu)), plaq_s(L, links, i, pn, mm)));"),
+    ("leaf 2 orientation flipped", "plaq_s(L, links, i, mn, pm)", "plaq_s(L, links, i, pm, mn)"),
+    ("no trace subtraction in P_ah", "for (int i = 0; i < 3; i++) r.a[i][i] -= t;", "(void)t;"),
+    ("force sign",
+     "F[i * 4 + mu] = m_scale(-1.0, m_proj_ah(omega(L, links, i, mu)));",
+     "F[i * 4 + mu] = m_proj_ah(omega(L, links, i, mu));"),
+    ("exponential truncated", "for (int k = 1; k <= 16; k++) {", "for (int k = 1; k <= 2; k++) {"),
+    ("twist site shifted",
+     "if (n[mu] != L->base[mu] || n[nu] != L->base[nu]) return 1.0;",
+     "if (n[mu] != L->base[mu] || n[nu] != (L->base[nu] + 1) % L->d[nu]) return 1.0;"),
+    ("Levi-Civita sign", "q += 0.5 * eps * creal", "q -= 0.5 * eps * creal"),
+    ("E factor 1/2 dropped", "e += 0.5 * creal(m_tr(m_mul(G[m][n], G[m][n])));",
+     "e += creal(m_tr(m_mul(G[m][n], G[m][n])));"),
+    ("plaquette normalisation", "out[1] = p / (18.0 * V);", "out[1] = p / (9.0 * V);"),
+    ("lower staple neighbour", "long ipm_mn = step(L, ipm, nu, -1);", "long ipm_mn = step(L, i, nu, -1);"),
+    ("no short final step", "int has_short = (t_end - t_last) > 1e-12;", "int has_short = 0;"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(tmp_path, name, old, new):
+    for sub in ("oracle", "tests", "paper_2107_03747_amd"):
+        shutil.copytree(os.path.join(ROOT, sub), tmp_path / sub,
+                        ignore=shutil.ignore_patterns("*.so", "*.so.tmp", "__pycache__"))
+    shutil.copy(os.path.join(ROOT, "pytest.ini"), tmp_path)
+    src = tmp_path / "oracle" / "tgf_oracle.c"
+    text = src.read_text()
+    assert text.count(old) >= 1, f"mutation site for '{name}' not found"
+    src.write_text(text.replace(old, new, 1))
+    r = subprocess.run([sys.executable, "-m", "pytest", "tests/test_oracle_pins.py", "-q", "-x",
+                        "-p", "no:cacheprovider"], cwd=tmp_path, capture_output=True, text=True,
+                       timeout=900)
+    assert r.returncode != 0, f"planted mistake '{name}' was not caught:\n{r.stdout[-2000:]}"
