@@ -181,6 +181,39 @@ const char *tgf_variant_name(int32_t variant);
  * calibration kernel for HBM counters.  Enqueued only. */
 tgf_status tgf_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, void *hip_stream);
 
+/* Topological charge per slice of direction dir (0..3; the paper uses a long
+ * direction): q_host[cfg * max_slices + s] = (1/16 pi^2) sum over the sites with
+ * n_dir = s of Tr G G~ (the charge density of eq. qlatt summed over the three
+ * other directions, sec. 4), for s < dims[dir]; later entries are zero.  FP64
+ * sums in a fixed order.  Synchronises. */
+tgf_status tgf_slice_charge(tgf_ctx *c, int32_t dir, double *q_host, int32_t max_slices);
+
+/* --- ensemble statistics (host FP64, no device work) --------------------- */
+
+/* Lattice normalisation N(c, Lt) of the twisted gradient-flow coupling
+ * (sec. 3.1, eq. latt_norm): N^{-1} = c^4/128 sum_{mu!=nu} sum'_q
+ * exp(-c^2 Lt^2 qhat^2/4) sin^2(q_nu) cos^2(q_mu/2) / qhat^2 over
+ * q_mu = 2 pi n_mu / Lt, n_mu = 0..Lt-1, leaving out the momenta whose two
+ * twisted-plane (directions 0, 1) components both have Lt q_i a multiple of
+ * 2 pi N (n_i = 0 mod N).  Lt <= 512. */
+tgf_status tgf_latt_norm(double c, int32_t Lt, int32_t N, double *out);
+
+/* lambda_TGF = N(c, Lt) <t2E delta_Q> / (3 <delta_Q>) with delta_Q = 1 iff
+ * |Q| < 0.5 (sec. 3.1, eq. lambdat_latt), over n configurations' t2E[n], Q[n]
+ * at sqrt(8t) = c Lt; err (may be NULL): delete-one jackknife error.
+ * TGF_E_STATE if no configuration has |Q| < 0.5. */
+tgf_status tgf_coupling(const double *t2E, const double *Q, int32_t n, double c, int32_t Lt,
+                        int32_t N, double *lambda, double *err);
+
+/* C(x0) = <q(x0) q(0) delta_Q> / <delta_Q> (sec. 4, eq. qcorr), averaged over
+ * the origin: q[k * ld + x] is configuration k's slice charge (x < T), Q[k] its
+ * total charge; C[T] and err[T] (jackknife, may be NULL) are written. */
+tgf_status tgf_charge_correlator(const double *q, const double *Q, int32_t n, int32_t T,
+                                 int32_t ld, double *C, double *err);
+
+/* Message of the last failing statistics call ("" if none). */
+const char *tgf_stats_last_error(void);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char *tgf_last_error(void);
 

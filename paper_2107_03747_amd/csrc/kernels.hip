@@ -767,6 +767,61 @@ __global__ __launch_bounds__(192) void measure_kernel(const CfgDesc *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Topological charge per slice: q(s) = (1/16 pi^2) sum_{n : n_dir = s} Tr G G~
+// (eq. qlatt restricted to one slice).  Block (chunk, s) sums chunk_sites
+// sites of slice s; the sites of a slice are enumerated over the three other
+// directions in increasing order.  FP64 partials, summed in a fixed order.
+template <class R, int NE>
+__global__ __launch_bounds__(256) void slice_charge_kernel(const CfgDesc *__restrict__ cfgs, int ci,
+                                                           int dir, int chunk_sites,
+                                                           double *__restrict__ partials) {
+    const CfgDesc c = cfgs[ci];
+    const int s = blockIdx.y;
+    const int dd = c.d[dir];
+    const int S = c.V / dd;
+    // the other three directions, increasing
+    const int o0 = dir == 0 ? 1 : 0;
+    const int o1 = dir <= 1 ? 2 : 1;
+    const int o2 = dir == 3 ? 2 : 3;
+    int st[4];
+    st[0] = 1; st[1] = c.d[0]; st[2] = c.d[0] * c.d[1]; st[3] = st[2] * c.d[2];
+    const int sa = st[o0], sb = st[o1], sc = st[o2], sd = st[dir];
+    const int da = c.d[o0], db = c.d[o1];
+    const Links<R, NE> W{as_global<R>((const void *)(c.cur ? c.W[1] : c.W[0])), c.stride};
+    double acc = 0;
+    const int j0 = blockIdx.x * chunk_sites;
+    const int j1 = min(j0 + chunk_sites, S);
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) {
+        const int na = j % da, r = j / da;
+        const int nb = r % db, nc = r / db;
+        const int i = na * sa + nb * sb + nc * sc + s * sd;
+        const Geo g = make_geo(c, i);
+        double v[4];
+        measure_pair<R, NE, 0>(W, c, g, v);
+        acc += v[1];
+        measure_pair<R, NE, 1>(W, c, g, v);
+        acc += v[1];
+        measure_pair<R, NE, 2>(W, c, g, v);
+        acc += v[1];
+    }
+    acc = wave_sum(acc);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partials[(size_t)s * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void slice_finalize_kernel(const double *__restrict__ partials, int n_slices, int chunks,
+                                      double *__restrict__ out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_slices) return;
+    double t = 0;
+    for (int k = 0; k < chunks; k++) t += partials[(size_t)s * chunks + k];
+    out[s] = t;
+}
+
 // One work-group per configuration: fixed-order sum of its tile partials.
 __global__ __launch_bounds__(256) void finalize_kernel(const CfgDesc *__restrict__ cfgs,
                                                        const int *__restrict__ tile_start,
@@ -1065,6 +1120,28 @@ hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(check_final_kernel, dim3(1), dim3(256), 0, s, partials, ntiles, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_charge(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs, int ci,
+                               int dir, int n_slices, int slice_sites, double *partials,
+                               double *out) {
+    const int chunk = 1024;
+    const int chunks = (slice_sites + chunk - 1) / chunk;
+    dim3 grid(chunks, n_slices);
+    if (p == P_F64)
+        hipLaunchKernelGGL((slice_charge_kernel<double, 9>), grid, dim3(256), 0, s, cfgs, ci, dir,
+                           chunk, partials);
+    else if (c12)
+        hipLaunchKernelGGL((slice_charge_kernel<float, 6>), grid, dim3(256), 0, s, cfgs, ci, dir,
+                           chunk, partials);
+    else
+        hipLaunchKernelGGL((slice_charge_kernel<float, 9>), grid, dim3(256), 0, s, cfgs, ci, dir,
+                           chunk, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(slice_finalize_kernel, dim3((n_slices + 63) / 64), dim3(64), 0, s, partials,
+                       n_slices, chunks, out);
     return hipGetLastError();
 }
 

@@ -51,6 +51,13 @@ hipError_t launch_unpack(Prec p, bool c12, hipStream_t s, const void *W, void *d
 hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void *src, int V,
                         int stride, double *partials, double *out);
 
+// Topological charge per slice of direction `dir` for config ci (exec-order
+// descriptor at cfgs[ci]); partials need n_slices * ceil(slice_sites/1024)
+// doubles, out n_slices doubles.
+hipError_t launch_slice_charge(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs, int ci,
+                               int dir, int n_slices, int slice_sites, double *partials,
+                               double *out);
+
 hipError_t launch_fill_int(hipStream_t s, int *dst, int n, int value);
 hipError_t launch_copy(hipStream_t s, void *dst, const void *src, size_t bytes);
 

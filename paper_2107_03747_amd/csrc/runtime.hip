@@ -716,6 +716,48 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
     return TGF_OK;
 }
 
+tgf_status tgf_slice_charge(tgf_ctx *c, int32_t dir, double *q_host, int32_t max_slices) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if (dir < 0 || dir > 3) return fail(TGF_E_INVAL, "dir must be 0..3");
+    if (!q_host) return fail(TGF_E_INVAL, "q_host is NULL");
+    size_t total = 0;
+    for (int k = 0; k < c->n_cfg; k++) {
+        const CfgHost &h = c->L.cfg[k];
+        if (!h.loaded) return fail(TGF_E_STATE, "config " + std::to_string(k) + " not loaded");
+        if (h.d[dir] > max_slices)
+            return fail(TGF_E_SIZE, "max_slices smaller than the extent of direction dir");
+        total += (size_t)h.d[dir];
+    }
+    if (total > (size_t)6 * kMaxRows * c->n_cfg)
+        return fail(TGF_E_UNSUPPORTED, "too many slices in total");
+    std::vector<int> order(c->n_cfg);
+    for (int k = 0; k < c->n_cfg; k++) order[k] = k;
+    std::vector<int> ts;
+    if ((s = upload_tables(c, order, nullptr, ts))) return s;
+    size_t off = 0;
+    for (int k = 0; k < c->n_cfg; k++) {
+        const CfgHost &h = c->L.cfg[k];
+        HIP_TRY(launch_slice_charge(c->prec(), c->c12(), c->stream, c->d_desc(), k, dir,
+                                    h.d[dir], h.V / h.d[dir], c->d_partials(), c->d_rows() + off));
+        off += (size_t)h.d[dir];
+    }
+    if ((s = ensure_stage(c, sizeof(double) * total))) return s;
+    HIP_TRY(hipMemcpyAsync(c->h_stage, c->d_rows(), sizeof(double) * total, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double *src = (const double *)c->h_stage;
+    off = 0;
+    for (int k = 0; k < c->n_cfg; k++) {
+        const int d = c->L.cfg[k].d[dir];
+        for (int t = 0; t < max_slices; t++)
+            q_host[(size_t)k * max_slices + t] = t < d ? src[off + t] : 0.0;
+        off += (size_t)d;
+    }
+    return TGF_OK;
+}
+
 tgf_status tgf_get_timing(tgf_ctx *c, tgf_timing *out) {
     g_err.clear();
     tgf_status s = check_ctx(c);

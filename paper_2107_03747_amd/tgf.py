@@ -121,6 +121,16 @@ _sig = {
     "tgf_variant_count": (_I, []),
     "tgf_variant_name": (ctypes.c_char_p, [_I]),
     "tgf_stream_copy": (_st, [_P, _P, ctypes.c_size_t, _P]),
+    "tgf_slice_charge": (_st, [_P, _I, ctypes.POINTER(ctypes.c_double), _I]),
+    "tgf_latt_norm": (_st, [ctypes.c_double, _I, _I, ctypes.POINTER(ctypes.c_double)]),
+    "tgf_coupling": (_st, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _I,
+                           ctypes.c_double, _I, _I, ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double)]),
+    "tgf_charge_correlator": (_st, [ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), _I, _I, _I,
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
+    "tgf_stats_last_error": (ctypes.c_char_p, []),
     "tgf_last_error": (ctypes.c_char_p, []),
     "tgf_destroy": (None, [_P]),
 }
@@ -274,6 +284,15 @@ class Flow:
                                   shape=(max_rows * self.n * 6,))
         return a.reshape(max_rows, self.n, 6)[: nr.value].copy()
 
+    def slice_charge(self, dir=3):
+        """Topological charge per slice of direction dir -> [n_cfg, max extent]."""
+        ms = max(d[dir] for d in self.dims)
+        out = np.zeros((self.n, ms))
+        self._sync_in()
+        check(tgf_slice_charge(self._ctx, int(dir),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ms))
+        return out
+
     def timing(self):
         t = tgf_timing()
         check(tgf_get_timing(self._ctx, ctypes.byref(t)))
@@ -295,6 +314,43 @@ class Flow:
     @property
     def variant(self):
         return int(tgf_get_variant(self._ctx))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check_stats(status):
+    if status != TGF_OK:
+        raise TGFError(status, tgf_stats_last_error().decode())
+
+
+def latt_norm(c, Lt, N=3):
+    """Lattice normalisation N(c, Lt) of the coupling (host FP64)."""
+    out = ctypes.c_double()
+    _check_stats(tgf_latt_norm(float(c), int(Lt), int(N), ctypes.byref(out)))
+    return out.value
+
+
+def coupling(t2E, Q, c, Lt, N=3):
+    """(lambda_TGF, jackknife error) from per-configuration t^2 E and Q."""
+    t2E = np.ascontiguousarray(t2E, dtype=np.float64)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    lam, err = ctypes.c_double(), ctypes.c_double()
+    _check_stats(tgf_coupling(_dptr(t2E), _dptr(Q), len(t2E), float(c), int(Lt), int(N),
+                              ctypes.byref(lam), ctypes.byref(err)))
+    return lam.value, err.value
+
+
+def charge_correlator(q, Q):
+    """C(x0) and its jackknife error from slice charges q[n_cfg, T] and Q[n_cfg]."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    n, T = q.shape
+    C = np.zeros(T)
+    E = np.zeros(T)
+    _check_stats(tgf_charge_correlator(_dptr(q), _dptr(Q), n, T, T, _dptr(C), _dptr(E)))
+    return C, E
 
 
 def variant_names():
