@@ -424,13 +424,22 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
         if (!links[k]) return fail(TGF_E_INVAL, "links pointer is NULL");
         if (!std::isfinite(t0[k]) || t0[k] < 0) return fail(TGF_E_INVAL, "t0 must be >= 0");
     }
-    // check every input before touching storage
-    double worst[2] = {0, 0};
-    int bad = -1;
+    // check every input before touching storage: each check writes its two
+    // defects to its own slot of the rows region, one readback for all
     for (size_t k = 0; k < cfgs.size(); k++) {
-        double d[2];
-        tgf_status s = run_check(c, cfgs[k], links[k], true, d);
-        if (s) return s;
+        const CfgHost &h = c->L.cfg[cfgs[k]];
+        HIP_TRY(launch_check(c->prec(), c->c12(), true, c->stream, links[k], h.V, h.stride,
+                             c->d_partials(), c->d_rows() + 2 * k));
+    }
+    tgf_status st0 = ensure_stage(c, sizeof(double) * 2 * cfgs.size());
+    if (st0) return st0;
+    HIP_TRY(hipMemcpyAsync(c->h_stage, c->d_rows(), sizeof(double) * 2 * cfgs.size(),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int bad = -1;
+    double worst[2] = {0, 0};
+    for (size_t k = 0; k < cfgs.size(); k++) {
+        const double *d = (const double *)c->h_stage + 2 * k;
         if (!(d[0] <= 1e-10) || !(d[1] <= 1e-10)) {
             bad = cfgs[k];
             worst[0] = d[0];
