@@ -48,6 +48,11 @@ def _load():
         lib.oracle_rk3_step.argtypes = [P, I4, I4, I4, ctypes.c_double]
         lib.oracle_flow.argtypes = [P, I4, I4, I4, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, P, ctypes.c_int]
+        lib.oracle_mc.argtypes = [P, I4, I4, I4, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_ulonglong, ctypes.c_uint, ctypes.c_uint]
+        lib.oracle_or_sweeps.argtypes = [P, I4, I4, I4, ctypes.c_int]
+        lib.oracle_su2_samples.argtypes = [ctypes.c_double, ctypes.c_ulonglong, ctypes.c_int, P]
+        lib.oracle_philox.argtypes = [P, ctypes.c_uint, ctypes.c_uint, P]
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_get_threads.restype = ctypes.c_int
         _lib = lib
@@ -142,3 +147,35 @@ def flow(links, dims, eps, t_end, meas_dt=0.0, t0=0.0, twist=PAPER_TWIST, base=N
     if n < 0:
         raise RuntimeError(f"oracle_flow failed ({n})")
     return rows[:n].copy()
+
+
+def mc(links, dims, b, n_hybrid, n_or, seed, sweep0=0, cfg=0, twist=PAPER_TWIST, base=None):
+    """Hybrid over-relaxation in place: n_hybrid x (1 heat-bath + n_or OR sweeps),
+    beta = 18 b (b = 1/lambda_0, sec. 3.1)."""
+    _check_links(links, dims)
+    rc = _load().oracle_mc(links.ctypes.data, _ivec(dims, 4), _ivec(twist, 6), _ivec(base, 4),
+                           18.0 * float(b), int(n_hybrid), int(n_or), int(seed), int(sweep0),
+                           int(cfg))
+    if rc:
+        raise RuntimeError(f"oracle_mc failed ({rc})")
+
+
+def or_sweeps(links, dims, n, twist=PAPER_TWIST, base=None):
+    _check_links(links, dims)
+    rc = _load().oracle_or_sweeps(links.ctypes.data, _ivec(dims, 4), _ivec(twist, 6),
+                                  _ivec(base, 4), int(n))
+    if rc:
+        raise RuntimeError(f"oracle_or_sweeps failed ({rc})")
+
+
+def su2_samples(alpha, seed, n):
+    out = np.zeros((n, 4))
+    _load().oracle_su2_samples(float(alpha), int(seed), int(n), out.ctypes.data)
+    return out
+
+
+def philox(ctr, k0, k1):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().oracle_philox(c.ctypes.data, int(k0), int(k1), out.ctypes.data)
+    return out

@@ -21,6 +21,9 @@
  *   clover E        E_cl = 1/2 Tr[G^cl G^cl], G^cl from four twisted
  *                   leaves (eq. gmunu)                              sec. 3.1
  *   charge Q        (1/16 pi^2) sum_n Tr{G^cl G~^cl}  (eq. qlatt)   sec. 3.1
+ *   Monte Carlo     hybrid over-relaxation: one heat-bath sweep, then
+ *                   over-relaxation sweeps (Cabibbo-Marinari SU(2)
+ *                   subgroups, checkerboard, Philox4x32-10)         sec. 3.1
  *
  * Readings where the paper is silent (both paths adopt them):
  *   - The twist site "x1 = x2 = 1" is 1-based; 0-based it is n_mu = n_nu = 0.
@@ -35,6 +38,10 @@
  *     s = sum_n sum_{mu<nu} Re Tr[1 - Z^* P]  (= g0^2 S_W / 2).
  *   - Schedule: steps of eps while t + eps <= t_end (+1e-12), then one short
  *     step to t_end; rows at grid multiples of meas_dt and at t_end.
+ *   - Monte Carlo (the paper names the algorithm, not its details): beta =
+ *     18 b; sweep order mu = 0..3, even then odd sites; subgroups (0,1),
+ *     (0,2), (1,2) in turn; the random-number counter layout stated at
+ *     mc_sweep.
  *
  * The exponential is scaling-and-squaring with a degree-16 Taylor sum: a
  * different method from the GPU library's.
@@ -378,6 +385,147 @@ static int rk3_step(const lat *L, cplx *links, double eps) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Monte Carlo: hybrid over-relaxation (sec. 3.1: one heat-bath sweep  */
+/* followed by n_or over-relaxation sweeps) with Cabibbo-Marinari      */
+/* SU(2) subgroups (0,1), (0,2), (1,2), on a checkerboard              */
+/*
+ * Local action of U_mu(n): -(beta/3) Re Tr[U_mu(n) S] with S the twisted
+ * staple sum (Omega = U S above), beta = 18 b (S_W = 3b sum_{mu!=nu} Tr[1 - Z^* P]).
+ * A subgroup update U -> A U (A in SU(2) on rows i, j) changes Re Tr[U S] by
+ * Re Tr[A W_ij] - Re Tr[W_ij] with W = U S; for A = a0 + i a.sigma,
+ * Re Tr[A W_ij] = a . c with c = (W_ii.re + W_jj.re, -(W_ij.im + W_ji.im),
+ * W_ji.re - W_ij.re, W_jj.im - W_ii.im).  Heat bath: A = Y C^ with C^ the SU(2)
+ * element of c/|c| and Y drawn with density ~ exp(alpha y0), alpha = beta |c|/3
+ * (Creutz for alpha < 2, Kennedy-Pendleton otherwise).  Over-relaxation:
+ * A = C^ C^, which keeps Re Tr[U S].
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11), counter
+ * (site, sweep, mu<<24 | subgroup<<16 | attempt, config), key = seed;
+ * u = (x + 1/2) 2^-32.
+ */
+typedef struct { unsigned int v[4]; } u4;
+
+static u4 philox4x32_10(u4 ctr, unsigned int k0, unsigned int k1) {
+    const unsigned int M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const unsigned int W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    for (int r = 0; r < 10; r++) {
+        if (r) { k0 += W0; k1 += W1; }
+        unsigned long long p0 = (unsigned long long)M0 * ctr.v[0];
+        unsigned long long p1 = (unsigned long long)M1 * ctr.v[2];
+        u4 o;
+        o.v[0] = (unsigned int)(p1 >> 32) ^ ctr.v[1] ^ k0;
+        o.v[1] = (unsigned int)p1;
+        o.v[2] = (unsigned int)(p0 >> 32) ^ ctr.v[3] ^ k1;
+        o.v[3] = (unsigned int)p0;
+        ctr = o;
+    }
+    return ctr;
+}
+
+static double u01(unsigned int x) { return ((double)x + 0.5) * (1.0 / 4294967296.0); }
+
+/* y0 with density ~ sqrt(1 - y0^2) exp(alpha y0) on [-1, 1], then a uniform
+ * direction for (y1, y2, y3); ctr.v[2] holds mu<<24 | subgroup<<16 */
+static void su2_draw(double alpha, u4 ctr, unsigned int k0, unsigned int k1, double y[4]) {
+    double y0 = 1.0;
+    int ok = 0;
+    for (unsigned int att = 0; att < 256 && !ok; att++) {
+        u4 c = ctr;
+        c.v[2] |= att;
+        u4 r = philox4x32_10(c, k0, k1);
+        double u1 = u01(r.v[0]), u2 = u01(r.v[1]), u3 = u01(r.v[2]), u4_ = u01(r.v[3]);
+        if (alpha < 1e-8) {
+            y0 = 2.0 * u1 - 1.0;
+            ok = u2 * u2 <= 1.0 - y0 * y0;
+        } else if (alpha < 2.0) {            /* Creutz */
+            double e = exp(-2.0 * alpha);
+            y0 = 1.0 + log(u1 * (1.0 - e) + e) / alpha;
+            ok = u2 * u2 <= 1.0 - y0 * y0;
+        } else {                             /* Kennedy-Pendleton */
+            double cs = cos(2.0 * PI * u2);
+            double X = -(log(u1) + cs * cs * log(u3)) / (2.0 * alpha);
+            y0 = 1.0 - 2.0 * X;
+            ok = u4_ * u4_ <= 1.0 - X;
+        }
+    }
+    if (!ok) { y[0] = 1; y[1] = y[2] = y[3] = 0; return; }
+    u4 c = ctr;
+    c.v[2] |= 0xFFFFu;
+    u4 r = philox4x32_10(c, k0, k1);
+    double ct = 2.0 * u01(r.v[0]) - 1.0, ph = 2.0 * PI * u01(r.v[1]);
+    double st = sqrt(fmax(0.0, 1.0 - ct * ct)), rr = sqrt(fmax(0.0, 1.0 - y0 * y0));
+    y[0] = y0;
+    y[1] = rr * st * cos(ph);
+    y[2] = rr * st * sin(ph);
+    y[3] = rr * ct;
+}
+
+/* SU(2) matrix of the unit quaternion a: [[a0 + i a3, a2 + i a1], [-a2 + i a1, a0 - i a3]] */
+static void q2m(const double a[4], cplx m[2][2]) {
+    m[0][0] = a[0] + I * a[3];
+    m[0][1] = a[2] + I * a[1];
+    m[1][0] = -a[2] + I * a[1];
+    m[1][1] = a[0] - I * a[3];
+}
+
+/* left-multiply rows i, j of X by the 2x2 matrix A */
+static void rows_mul(mat *X, int i, int j, cplx A[2][2]) {
+    for (int k = 0; k < 3; k++) {
+        cplx xi = X->a[i][k], xj = X->a[j][k];
+        X->a[i][k] = A[0][0] * xi + A[0][1] * xj;
+        X->a[j][k] = A[1][0] * xi + A[1][1] * xj;
+    }
+}
+
+static void update_link(const lat *L, cplx *links, long i, int mu, double beta, int heatbath,
+                        unsigned long long seed, unsigned int sweep, unsigned int cfg) {
+    mat W = omega(L, links, i, mu);          /* U S with the twist factors */
+    mat Um = U(links, i, mu);
+    const int sub[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int s = 0; s < 3; s++) {
+        int a = sub[s][0], b = sub[s][1];
+        double c[4];
+        c[0] = creal(W.a[a][a]) + creal(W.a[b][b]);
+        c[1] = -(cimag(W.a[a][b]) + cimag(W.a[b][a]));
+        c[2] = creal(W.a[b][a]) - creal(W.a[a][b]);
+        c[3] = cimag(W.a[b][b]) - cimag(W.a[a][a]);
+        double k = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + c[3] * c[3]);
+        if (!(k > 1e-300)) continue;
+        double ch[4] = {c[0] / k, c[1] / k, c[2] / k, c[3] / k};
+        cplx C[2][2], A[2][2];
+        q2m(ch, C);
+        if (heatbath) {
+            u4 ctr = {{(unsigned int)i, sweep, ((unsigned int)mu << 24) | ((unsigned int)s << 16), cfg}};
+            double y[4];
+            su2_draw(beta * k / 3.0, ctr, (unsigned int)seed, (unsigned int)(seed >> 32), y);
+            cplx Y[2][2];
+            q2m(y, Y);
+            for (int p = 0; p < 2; p++)
+                for (int q = 0; q < 2; q++) A[p][q] = Y[p][0] * C[0][q] + Y[p][1] * C[1][q];
+        } else {
+            for (int p = 0; p < 2; p++)
+                for (int q = 0; q < 2; q++) A[p][q] = C[p][0] * C[0][q] + C[p][1] * C[1][q];
+        }
+        rows_mul(&Um, a, b, A);
+        rows_mul(&W, a, b, A);
+    }
+    memcpy(links + (i * 4 + mu) * 9, &Um, sizeof Um);
+}
+
+static void mc_sweep(const lat *L, cplx *links, double beta, int heatbath,
+                     unsigned long long seed, unsigned int sweep, unsigned int cfg) {
+    for (int mu = 0; mu < 4; mu++)
+        for (int par = 0; par < 2; par++) {
+#pragma omp parallel for schedule(static)
+            for (long i = 0; i < L->V; i++) {
+                int n[4];
+                coords(L, i, n);
+                if (((n[0] + n[1] + n[2] + n[3]) & 1) != par) continue;
+                update_link(L, links, i, mu, beta, heatbath, seed, sweep, cfg);
+            }
+        }
+}
+
+/* ------------------------------------------------------------------ */
 /* exported entry points (ctypes)                                      */
 
 void oracle_set_threads(int n) {
@@ -492,4 +640,47 @@ int oracle_flow(cplx *links, const int dims[4], const int twist[6], const int ba
     }
 #undef EMIT
     return nr;
+}
+
+/* n_hybrid times: one heat-bath sweep (index sweep0 + h (1 + n_or)) and n_or
+ * over-relaxation sweeps; beta = 18 b.  All extents must be even. */
+int oracle_mc(cplx *links, const int dims[4], const int twist[6], const int base[4],
+              double beta, int n_hybrid, int n_or, unsigned long long seed,
+              unsigned int sweep0, unsigned int cfg) {
+    lat L;
+    if (lat_init(&L, dims, twist, base)) return -1;
+    for (int m = 0; m < 4; m++)
+        if (dims[m] % 2) return -1;
+    unsigned int sw = sweep0;
+    for (int h = 0; h < n_hybrid; h++) {
+        mc_sweep(&L, links, beta, 1, seed, sw++, cfg);
+        for (int o = 0; o < n_or; o++) mc_sweep(&L, links, beta, 0, seed, sw++, cfg);
+    }
+    return 0;
+}
+
+/* over-relaxation sweeps only (no random numbers) */
+int oracle_or_sweeps(cplx *links, const int dims[4], const int twist[6], const int base[4],
+                     int n) {
+    lat L;
+    if (lat_init(&L, dims, twist, base)) return -1;
+    for (int m = 0; m < 4; m++)
+        if (dims[m] % 2) return -1;
+    for (int o = 0; o < n; o++) mc_sweep(&L, links, 0.0, 0, 0, 0, 0);
+    return 0;
+}
+
+/* n draws of the SU(2) heat-bath quaternion for a fixed alpha (sampler test) */
+void oracle_su2_samples(double alpha, unsigned long long seed, int n, double *out) {
+    for (int k = 0; k < n; k++) {
+        u4 ctr = {{(unsigned int)k, 7u, 0u, 0u}};
+        su2_draw(alpha, ctr, (unsigned int)seed, (unsigned int)(seed >> 32), out + 4 * k);
+    }
+}
+
+/* raw Philox4x32-10 output */
+void oracle_philox(const unsigned int ctr[4], unsigned int k0, unsigned int k1, unsigned int out[4]) {
+    u4 c = {{ctr[0], ctr[1], ctr[2], ctr[3]}};
+    u4 r = philox4x32_10(c, k0, k1);
+    memcpy(out, r.v, sizeof r.v);
 }

@@ -2,8 +2,11 @@
 
 Each case plants one mistake in a scratch copy of the oracle's C source (a
 twist factor conjugated or moved, a leaf mis-oriented, an RK3 coefficient, a
-normalisation, a sign, a neighbour index, the schedule), rebuilds it, and
-requires the pin suite to fail.  CPU only; the real oracle is untouched.
+normalisation, a sign, a neighbour index, the schedule; for the Monte Carlo a
+subgroup vector, the heat-bath coupling, an acceptance test, the direction
+draw, the checkerboard, the SU(2) embedding), rebuilds it, and requires the
+pin suite of that part (tests/test_oracle_pins.py, tests/test_oracle_mc.py)
+to fail.  CPU only; the real oracle is untouched.
 """
 
 import os
@@ -45,9 +48,23 @@ MUTANTS = [
     ("no short final step", "int has_short = (t_end - t_last) > 1e-12;", "int has_short = 0;"),
 ]
 
+# Monte Carlo mistakes, caught by tests/test_oracle_mc.py
+MC_MUTANTS = [
+    ("subgroup vector component sign",
+     "c[2] = creal(W.a[b][a]) - creal(W.a[a][b]);", "c[2] = creal(W.a[a][b]) - creal(W.a[b][a]);"),
+    ("heat-bath alpha halved", "su2_draw(beta * k / 3.0,", "su2_draw(beta * k / 6.0,"),
+    ("Kennedy-Pendleton acceptance", "ok = u4_ * u4_ <= 1.0 - X;", "ok = u4_ <= 1.0 - X;"),
+    ("Creutz acceptance", "ok = u2 * u2 <= 1.0 - y0 * y0;\n        } else {",
+     "ok = u2 <= 1.0 - y0 * y0;\n        } else {"),
+    ("direction on a hemisphere", "double ct = 2.0 * u01(r.v[0]) - 1.0,", "double ct = u01(r.v[0]),"),
+    ("no checkerboard", "if (((n[0] + n[1] + n[2] + n[3]) & 1) != par) continue;",
+     "if (par) continue;"),
+    ("SU(2) embedding sign", "m[0][1] = a[2] + I * a[1];", "m[0][1] = -a[2] + I * a[1];"),
+    ("staple not updated between subgroups", "rows_mul(&W, a, b, A);", "(void)W;"),
+]
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_pins_catch_planted_mistake(tmp_path, name, old, new):
+
+def _run_mutant(tmp_path, name, old, new, pins):
     for sub in ("oracle", "tests", "paper_2107_03747_amd"):
         shutil.copytree(os.path.join(ROOT, sub), tmp_path / sub,
                         ignore=shutil.ignore_patterns("*.so", "*.so.tmp", "__pycache__"))
@@ -56,7 +73,17 @@ def test_pins_catch_planted_mistake(tmp_path, name, old, new):
     text = src.read_text()
     assert text.count(old) >= 1, f"mutation site for '{name}' not found"
     src.write_text(text.replace(old, new, 1))
-    r = subprocess.run([sys.executable, "-m", "pytest", "tests/test_oracle_pins.py", "-q", "-x",
+    r = subprocess.run([sys.executable, "-m", "pytest", pins, "-q", "-x",
                         "-p", "no:cacheprovider"], cwd=tmp_path, capture_output=True, text=True,
                        timeout=900)
     assert r.returncode != 0, f"planted mistake '{name}' was not caught:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(tmp_path, name, old, new):
+    _run_mutant(tmp_path, name, old, new, "tests/test_oracle_pins.py")
+
+
+@pytest.mark.parametrize("name,old,new", MC_MUTANTS, ids=[m[0] for m in MC_MUTANTS])
+def test_mc_pins_catch_planted_mistake(tmp_path, name, old, new):
+    _run_mutant(tmp_path, name, old, new, "tests/test_oracle_mc.py")
