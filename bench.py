@@ -101,7 +101,7 @@ def flops_per_site_step(storage, variant):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "su3_dev.h", "layout.h"):
+    for f in ("kernels.hip", "lattice_dev.h", "su3_dev.h", "layout.h"):
         with open(os.path.join(ROOT, "paper_2107_03747_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -222,6 +222,88 @@ def cpu_baseline(cfgs, inputs, gpu_rows, target_s=12.0):
     }, (max(errs) if errs else None), done
 
 
+# Monte Carlo (hybrid over-relaxation, FP64 full storage), per link update.
+# Bytes: one launch updates the V/2 links of one direction and parity and
+# needs every link of the lattice once (the three other directions at all
+# sites, its own direction at both parities) and writes V/2 links:
+# (4 V + V/2) x 144 B / (V/2) = 1296 B.  Flops: six staples (2484), Omega
+# (198), three subgroup updates (3 x 240); the heat bath's random numbers and
+# acceptance tests (integer Philox, log, cos) are not counted.
+MC_BYTES_PER_LINK = (4 + 0.5) * 144 / 0.5
+MC_FLOPS_PER_LINK = 2484 + 198 + 3 * 240
+MC_B = 0.5
+MC_N_OR = 3
+MC_CPU_CFGS = 16
+
+
+def time_mc(tgf, torch, cfgs, inputs, reps, cpu=True):
+    """Hybrid sweeps (1 heat bath + MC_N_OR over-relaxation) on the batch
+    geometry in FP64: wall time of `reps` hybrid sweeps after one warm-up.
+    cpu: also run the oracle's Monte Carlo on the first MC_CPU_CFGS
+    configurations for the warm-up hybrid sweep (same seed and counters) --
+    its time is the CPU baseline and its links are compared with the GPU's."""
+    f = tgf.Flow([c[0] for c in cfgs], "f64")
+    f.load_all(inputs)
+    sw = f.mc(MC_B, 1, MC_N_OR, seed=1)
+    torch.cuda.synchronize()
+    first = [f.store(k).cpu().numpy() for k in range(MC_CPU_CFGS)] if cpu else None
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sw = f.mc(MC_B, 1, MC_N_OR, seed=1, sweep0=sw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sweeps = reps * (1 + MC_N_OR)
+    links = 4 * sum(math.prod(c[0]) for c in cfgs)
+    rate = links * sweeps / dt
+    launch_ms = dt / (8 * sweeps) * 1e3
+    gbs = rate * MC_BYTES_PER_LINK / 1e9
+    tflops = rate * MC_FLOPS_PER_LINK / 1e12
+    out = {
+        "metric": "Monte Carlo link-updates/s (hybrid over-relaxation, FP64)",
+        "value": round(rate, 1),
+        "unit": "link-updates/s",
+        "b": MC_B,
+        "sweeps": sweeps,
+        "heatbath_per_hybrid": 1,
+        "overrelax_per_hybrid": MC_N_OR,
+        "ms_per_sweep": round(dt / sweeps * 1e3, 3),
+        "roofline": {
+            "kernel": "mc_kernel<mu>",
+            "bound": "hbm",
+            "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "alu_tflops": round(tflops, 2),
+            "alu_frac_fp64": round(tflops / ALU_PEAK_TFLOPS, 4),
+            "avg_launch_ms_wall": round(launch_ms, 4),
+            "bytes_per_link_update": MC_BYTES_PER_LINK,
+            "flops_per_link_update": MC_FLOPS_PER_LINK,
+        },
+    }
+    if cpu:
+        import numpy as np
+        import oracle
+        oracle.build(force=False)
+        oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+        tc, n, dmax = 0.0, 0, 0.0
+        for k in range(MC_CPU_CFGS):
+            d = cfgs[k][0]
+            U = inputs[k].cpu().numpy().copy()
+            t0 = time.perf_counter()
+            oracle.mc(U, d, MC_B, 1, MC_N_OR, 1, sweep0=0, cfg=k)
+            tc += time.perf_counter() - t0
+            n += 4 * math.prod(d) * (1 + MC_N_OR)
+            dmax = max(dmax, float(np.abs(first[k] - U).max()))
+        out["cpu_baseline"] = {"value": round(n / tc, 1), "unit": "link-updates/s",
+                               "cores": oracle.get_threads(), "kind": "oracle",
+                               "sample": f"configurations 0..{MC_CPU_CFGS - 1} of the batch "
+                                         f"(8x8x24x24), one hybrid sweep each (1 HB + "
+                                         f"{MC_N_OR} OR): {n} link updates in {tc:.2f} s"}
+        out["max_abs_dU_vs_oracle_sample"] = dmax
+    return out
+
+
 def copy_mode(tgf, torch, args):
     """Plain copy of a known size with the library's copy kernel: reads and
     writes `bytes` each per launch.  Used to calibrate the HBM counters."""
@@ -253,8 +335,11 @@ def main():
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--mode", choices=("flow", "copy"), default="flow",
-                    help="copy: time the library's plain HBM copy kernel (counter calibration)")
+    ap.add_argument("--no-mc", action="store_true")
+    ap.add_argument("--mc-reps", type=int, default=3)
+    ap.add_argument("--mode", choices=("flow", "copy", "mc"), default="flow",
+                    help="copy: time the library's plain HBM copy kernel (counter calibration); "
+                         "mc: time only the Monte Carlo on the batch geometry")
     ap.add_argument("--copy-gib", type=float, default=2.0)
     args = ap.parse_args()
 
@@ -276,6 +361,11 @@ def main():
     log(f"generating {len(cfgs)} configurations on the GPU")
     inputs = make_inputs(cfgs, "cuda")
     torch.cuda.synchronize()
+    if args.mode == "mc":
+        log(f"timing the Monte Carlo: {args.mc_reps} hybrid sweeps")
+        print(json.dumps(time_mc(tgf, torch, cfgs, inputs, args.mc_reps, cpu=not args.no_cpu)),
+              flush=True)
+        return
     site_updates = sum(math.prod(c[0]) * n_steps(c[3]) for c in cfgs)
     sites = sum(math.prod(c[0]) for c in cfgs)
 
@@ -376,6 +466,10 @@ def main():
         out["speedup_vs_fp64_plain"] = round(dt64 / dt, 3)
         out["t2E_max_rel_err_vs_fp64_gpu"] = float(rel.max())
         del f64
+
+    if not args.no_mc:
+        log("timing the Monte Carlo on the same geometry")
+        out["mc"] = time_mc(tgf, torch, cfgs, inputs, args.mc_reps, cpu=not args.no_cpu)
 
     if not args.no_cpu:
         log("CPU baseline (oracle)")

@@ -188,6 +188,23 @@ tgf_status tgf_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, voi
  * sums in a fixed order.  Synchronises. */
 tgf_status tgf_slice_charge(tgf_ctx *c, int32_t dir, double *q_host, int32_t max_slices);
 
+/* Monte Carlo generation (sec. 3.1): hybrid over-relaxation of the twisted
+ * Wilson action with bare coupling b = 1/lambda_0 (beta = 18 b), applied in
+ * place to the current links of every configuration of the context:
+ * n_hybrid times { one heat-bath sweep, then n_or over-relaxation sweeps }.
+ * The paper takes n_or = Lt (the long extent) and Lt such hybrid sweeps
+ * between measurements.  Updates are SU(2)-subgroup (Cabibbo-Marinari) on a
+ * checkerboard; random numbers are Philox4x32-10 keyed by seed, with the
+ * counter (site, sweep index, direction/subgroup/attempt, configuration
+ * index); sweeps are numbered from sweep0 (heat-bath sweep of hybrid h:
+ * sweep0 + h (1 + n_or)), so a chain continued with the next sweep0 is the
+ * same chain.  Requires TGF_F64_FULL storage, every configuration loaded and
+ * every extent even (TGF_E_INVAL / TGF_E_STATE otherwise, nothing enqueued);
+ * b >= 0 finite; sweep0 + n_hybrid (1 + n_or) <= 2^32.  Afterwards every
+ * configuration is at flow time 0.  Synchronises. */
+tgf_status tgf_mc(tgf_ctx *c, double b, int32_t n_hybrid, int32_t n_or, uint64_t seed,
+                  uint32_t sweep0);
+
 /* --- ensemble statistics (host FP64, no device work) --------------------- */
 
 /* Lattice normalisation N(c, Lt) of the twisted gradient-flow coupling

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
+#include <stdint.h>
 
 #include "layout.h"
 
@@ -57,6 +58,14 @@ hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void 
 hipError_t launch_slice_charge(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs, int ci,
                                int dir, int n_slices, int slice_sites, double *partials,
                                double *out);
+
+// One Monte Carlo launch: the links of direction mu on the sites of parity
+// par (0 even, 1 odd) of every configuration, heat bath (heatbath = 1) or
+// over-relaxation, in place in W[cur].  FP64 full storage only.  tile_start
+// counts tiles of 64 sites of one parity (ceil(V/2 / 64) per configuration).
+hipError_t launch_mc(hipStream_t s, const CfgDesc *cfgs, const int *tile_start, int n_cfg,
+                     int n_tiles, int mu, int par, int heatbath, double beta, uint64_t seed,
+                     uint32_t sweep);
 
 hipError_t launch_fill_int(hipStream_t s, int *dst, int n, int value);
 hipError_t launch_copy(hipStream_t s, void *dst, const void *src, size_t bytes);

@@ -339,11 +339,16 @@ tgf_status run_check(tgf_ctx *c, int cfg, const void *src, bool canon, double ou
 }
 
 // Upload descriptors + tile prefix of the given exec order.
+// half_sites: the tiles cover the V/2 sites of one parity (Monte Carlo).
 tgf_status upload_tables(tgf_ctx *c, const std::vector<int> &order, const std::vector<Plan> *plans,
-                         std::vector<int> &tile_start) {
+                         std::vector<int> &tile_start, bool half_sites = false) {
     const int n = (int)order.size();
     tile_start.assign(n + 1, 0);
-    for (int k = 0; k < n; k++) tile_start[k + 1] = tile_start[k] + c->L.cfg[order[k]].tiles;
+    for (int k = 0; k < n; k++) {
+        const CfgHost &h = c->L.cfg[order[k]];
+        const int tiles = half_sites ? (h.V / 2 + 63) / 64 : h.tiles;
+        tile_start[k + 1] = tile_start[k] + tiles;
+    }
     size_t bytes = sizeof(CfgDesc) * n + sizeof(int) * (n + 1);
     tgf_status st = ensure_stage(c, bytes);
     if (st) return st;
@@ -764,6 +769,43 @@ tgf_status tgf_slice_charge(tgf_ctx *c, int32_t dir, double *q_host, int32_t max
             q_host[(size_t)k * max_slices + t] = t < d ? src[off + t] : 0.0;
         off += (size_t)d;
     }
+    return TGF_OK;
+}
+
+tgf_status tgf_mc(tgf_ctx *c, double b, int32_t n_hybrid, int32_t n_or, uint64_t seed,
+                  uint32_t sweep0) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if (c->st != TGF_F64_FULL)
+        return fail(TGF_E_INVAL, "Monte Carlo needs TGF_F64_FULL storage");
+    if (!std::isfinite(b) || b < 0) return fail(TGF_E_INVAL, "b must be finite and >= 0");
+    if (n_hybrid < 0 || n_or < 0) return fail(TGF_E_INVAL, "n_hybrid and n_or must be >= 0");
+    const uint64_t sweeps = (uint64_t)n_hybrid * (uint64_t)(1 + (int64_t)n_or);
+    if ((uint64_t)sweep0 + sweeps > (1ull << 32))
+        return fail(TGF_E_INVAL, "sweep counter would pass 2^32");
+    for (int k = 0; k < c->n_cfg; k++) {
+        const CfgHost &h = c->L.cfg[k];
+        if (!h.loaded) return fail(TGF_E_STATE, "config " + std::to_string(k) + " not loaded");
+        for (int m = 0; m < 4; m++)
+            if (h.d[m] % 2)
+                return fail(TGF_E_INVAL, "config " + std::to_string(k) +
+                                             ": the checkerboard needs even extents");
+    }
+    std::vector<int> order(c->n_cfg);
+    for (int k = 0; k < c->n_cfg; k++) order[k] = k;
+    std::vector<int> ts;
+    if ((s = upload_tables(c, order, nullptr, ts, true))) return s;
+    const double beta = 18.0 * b;
+    uint32_t sweep = sweep0;
+    for (int32_t h = 0; h < n_hybrid; h++)
+        for (int32_t o = 0; o <= n_or; o++, sweep++)
+            for (int mu = 0; mu < 4; mu++)
+                for (int par = 0; par < 2; par++)
+                    HIP_TRY(launch_mc(c->stream, c->d_desc(), c->d_tiles(), c->n_cfg,
+                                      ts[c->n_cfg], mu, par, o == 0 ? 1 : 0, beta, seed, sweep));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < c->n_cfg; k++) c->L.cfg[k].t = 0;
     return TGF_OK;
 }
 

@@ -122,6 +122,7 @@ _sig = {
     "tgf_variant_name": (ctypes.c_char_p, [_I]),
     "tgf_stream_copy": (_st, [_P, _P, ctypes.c_size_t, _P]),
     "tgf_slice_charge": (_st, [_P, _I, ctypes.POINTER(ctypes.c_double), _I]),
+    "tgf_mc": (_st, [_P, ctypes.c_double, _I, _I, ctypes.c_uint64, ctypes.c_uint32]),
     "tgf_latt_norm": (_st, [ctypes.c_double, _I, _I, ctypes.POINTER(ctypes.c_double)]),
     "tgf_coupling": (_st, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _I,
                            ctypes.c_double, _I, _I, ctypes.POINTER(ctypes.c_double),
@@ -292,6 +293,14 @@ class Flow:
         check(tgf_slice_charge(self._ctx, int(dir),
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ms))
         return out
+
+    def mc(self, b, n_hybrid=1, n_or=0, seed=0, sweep0=0):
+        """Hybrid over-relaxation in place on every configuration: n_hybrid x
+        (one heat-bath sweep + n_or over-relaxation sweeps), beta = 18 b; needs
+        f64 storage and even extents.  Returns the next free sweep index."""
+        self._sync_in()
+        check(tgf_mc(self._ctx, float(b), int(n_hybrid), int(n_or), int(seed), int(sweep0)))
+        return int(sweep0) + int(n_hybrid) * (1 + int(n_or))
 
     def timing(self):
         t = tgf_timing()

@@ -60,3 +60,16 @@ def fd_force_components(U, dims, site, mu, twist=(1, 0, 0, 0, 0, 0), h=1e-4):
             vals.append(action(V, dims, twist))
         d[a] = (vals[0] - vals[1]) / (2 * h)
     return d
+
+
+def u_strong(beta, n=256):
+    """(1/3) <Re Tr U> under exp((beta/3) Re Tr U) dU on SU(3), by the Weyl
+    integration formula (eigenphases t1, t2, t3 = -t1 - t2, weight |Delta|^2);
+    the periodic trapezoid rule converges spectrally."""
+    th = 2 * np.pi * np.arange(n) / n
+    t1, t2 = np.meshgrid(th, th, indexing="ij")
+    z = [np.exp(1j * t1), np.exp(1j * t2), np.exp(-1j * (t1 + t2))]
+    vd = np.abs((z[0] - z[1]) * (z[0] - z[2]) * (z[1] - z[2])) ** 2
+    tr = (z[0] + z[1] + z[2]).real
+    w = vd * np.exp(beta / 3 * tr)
+    return float((tr * w).sum() / w.sum() / 3)

@@ -1,0 +1,80 @@
+"""GPU parity at the benchmark's full size and launch configuration: the
+96-configuration ensemble batch (64 x 8x8x24x24, 16 x 6x6x18x18,
+16 x 10x10x30x30, near-identity links, flow to c = 0.3), FP32 12-real
+storage, one HIP graph per flow, the autotuned stage variant, FP64
+reunitarisation every 10 steps -- exactly what bench.py times.
+
+* every configuration vs the FP64 GPU path (itself oracle-checked): t^2 E <= 1e-5;
+* sampled configurations of each L vs the FP64 CPU oracle (whole flows for
+  L = 6 and 8, the first 0.2 of flow time for L = 10): t^2 E <= 1e-5;
+* sampled configurations flowed alone give bitwise the batch's rows.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import bench                                       # noqa: E402
+import oracle                                      # noqa: E402
+from paper_2107_03747_amd import tgf               # noqa: E402
+
+oracle.set_threads(16)
+T2E = tgf.OBS_FIELDS.index("t2E")
+
+
+@pytest.fixture(scope="module")
+def batch():
+    cfgs = bench.batch_workload()
+    inputs = bench.make_inputs(cfgs, "cuda")
+    t_end = [c[3] for c in cfgs]
+    f = tgf.Flow([c[0] for c in cfgs], "f32c12")
+    f.load_all(inputs)
+    v = f.autotune(None)
+    f.load_all(inputs)
+    rows = f.flow(bench.EPS, t_end, 0.1, 10)
+    print(f"  batch flowed with variant {tgf.variant_names()[v]}", flush=True)
+    return cfgs, inputs, rows, v
+
+
+def test_batch_vs_fp64_gpu(batch):
+    cfgs, inputs, rows, _ = batch
+    g = tgf.Flow([c[0] for c in cfgs], "f64")
+    g.load_all(inputs)
+    r64 = g.flow(bench.EPS, [c[3] for c in cfgs], 0.1, 0)
+    assert rows.shape == r64.shape
+    pos = r64[:, :, 0] > 0
+    rel = np.abs(rows[:, :, T2E] - r64[:, :, T2E])[pos] / np.abs(r64[:, :, T2E][pos])
+    print(f"  max rel t2E over 96 configs: {rel.max():.3g}", flush=True)
+    assert rel.max() <= 1e-5
+
+
+@pytest.mark.parametrize("k", [0, 64, 80])
+def test_batch_samples_vs_oracle(batch, k):
+    cfgs, inputs, rows, _ = batch
+    dims, _, _, t_end = cfgs[k]
+    t_stop = t_end if dims[0] <= 8 else 0.2
+    ref = oracle.flow(inputs[k].cpu().numpy().copy(), dims, bench.EPS, t_stop, 0.1)
+    got = rows[: ref.shape[0], k]
+    if t_stop == t_end:
+        n = int(np.argmax(np.abs(rows[:, k, 0] - t_end) < 1e-9)) + 1
+        got = rows[:n, k]
+    assert np.allclose(got[:, 0], ref[:, 0], atol=1e-12)
+    pos = ref[:, 0] > 0
+    rel = np.abs(got[pos, T2E] - ref[pos, 2]) / np.abs(ref[pos, 2])
+    print(f"  config {k} {dims}: max rel t2E vs oracle {rel.max():.3g}", flush=True)
+    assert rel.max() <= 1e-5
+
+
+@pytest.mark.parametrize("k", [5, 70, 90])
+def test_batch_samples_equal_solo(batch, k):
+    cfgs, inputs, rows, v = batch
+    dims, _, _, t_end = cfgs[k]
+    f = tgf.Flow([dims], "f32c12")
+    f.set_variant(v)
+    f.load(0, inputs[k])
+    solo = f.flow(bench.EPS, t_end, 0.1, 10)
+    assert np.array_equal(rows[: solo.shape[0], k], solo[:, 0])

@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 
 import oracle
+from brute import u_strong
 from paper_2107_03747_amd import gen
 
 KAT = [
@@ -116,19 +117,6 @@ def test_heatbath_beta0_is_haar():
     assert abs(np.mean(np.abs(tr) ** 2) - 1) < 5 * np.sqrt(1.0 / n)
     assert abs(np.mean(tr ** 3) - 1) < 5 * np.sqrt(6.0 / n)
     assert abs(np.mean(np.abs(tr) ** 4) - 2) < 5 * np.sqrt(22.0 / n)
-
-
-def u_strong(beta, n=256):
-    """(1/3) <Re Tr U> under exp((beta/3) Re Tr U) dU on SU(3), by the Weyl
-    integration formula (eigenphases t1, t2, t3 = -t1 - t2, weight |Delta|^2);
-    the periodic trapezoid rule converges spectrally."""
-    th = 2 * np.pi * np.arange(n) / n
-    t1, t2 = np.meshgrid(th, th, indexing="ij")
-    z = [np.exp(1j * t1), np.exp(1j * t2), np.exp(-1j * (t1 + t2))]
-    vd = np.abs((z[0] - z[1]) * (z[0] - z[2]) * (z[1] - z[2])) ** 2
-    tr = (z[0] + z[1] + z[2]).real
-    w = vd * np.exp(beta / 3 * tr)
-    return float((tr * w).sum() / w.sum() / 3)
 
 
 def test_u_strong_series():
