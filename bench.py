@@ -35,6 +35,17 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -192,7 +203,7 @@ def cpu_baseline(cfgs, inputs, gpu_rows, target_s=12.0):
         return {
             "value": V0 * nst / dt,
             "unit": "site-updates/s",
-            "cores": oracle.get_threads(),
+            "cores": oracle.get_threads(), "host_cpu": host_cpu(),
             "kind": "oracle",
             "sample": f"config 0 ({'x'.join(map(str, dims0))}), first {nst} FP64 RK3 steps of "
                       f"eps={EPS} and one measurement: {V0 * nst} site-updates in {dt:.1f} s",
@@ -214,7 +225,7 @@ def cpu_baseline(cfgs, inputs, gpu_rows, target_s=12.0):
     return {
         "value": su / elapsed,
         "unit": "site-updates/s",
-        "cores": oracle.get_threads(),
+        "cores": oracle.get_threads(), "host_cpu": host_cpu(),
         "kind": "oracle",
         "sample": f"configs 0..{done - 1} of the batch ({', '.join(shapes)}), whole FP64 flows "
                   f"with eps={EPS} from t=0 to t_end and one measurement each: {su} site-updates "
@@ -296,7 +307,7 @@ def time_mc(tgf, torch, cfgs, inputs, reps, cpu=True):
             n += 4 * math.prod(d) * (1 + MC_N_OR)
             dmax = max(dmax, float(np.abs(first[k] - U).max()))
         out["cpu_baseline"] = {"value": round(n / tc, 1), "unit": "link-updates/s",
-                               "cores": oracle.get_threads(), "kind": "oracle",
+                               "cores": oracle.get_threads(), "host_cpu": host_cpu(), "kind": "oracle",
                                "sample": f"configurations 0..{MC_CPU_CFGS - 1} of the batch "
                                          f"(8x8x24x24), one hybrid sweep each (1 HB + "
                                          f"{MC_N_OR} OR): {n} link updates in {tc:.2f} s"}

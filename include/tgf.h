@@ -228,6 +228,11 @@ tgf_status tgf_coupling(const double *t2E, const double *Q, int32_t n, double c,
 tgf_status tgf_charge_correlator(const double *q, const double *Q, int32_t n, int32_t T,
                                  int32_t ld, double *C, double *err);
 
+/* Topological susceptibility chi = <Q^2> / V (sec. 4.2) over the n
+ * configurations' total charges Q[n] (no sector filter), V the number of
+ * sites; err (may be NULL): delete-one jackknife error (NaN for n = 1). */
+tgf_status tgf_susceptibility(const double *Q, int32_t n, double V, double *chi, double *err);
+
 /* Message of the last failing statistics call ("" if none). */
 const char *tgf_stats_last_error(void);
 

@@ -93,6 +93,16 @@ def charge_correlator(q, Q):
     return C, E
 
 
+def susceptibility(Q, V):
+    """chi = <Q^2>/V (sec. 4.2), delete-one jackknife error."""
+    Q = np.asarray(Q, float)
+    n = len(Q)
+    chi = float(np.mean(Q ** 2) / V)
+    jk = np.array([np.mean(np.delete(Q, k) ** 2) / V for k in range(n)])
+    err = math.sqrt((n - 1) / n * np.sum((jk - jk.mean()) ** 2))
+    return chi, err
+
+
 def slice_charges(qdens, dims, direction=3):
     """q(x0) = sum of the per-site charge density over the slice n_dir = x0."""
     d0, d1, d2, d3 = dims

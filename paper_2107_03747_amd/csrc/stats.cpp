@@ -11,6 +11,7 @@
 //        delta_Q = 1 iff |Q| < 0.5 (sec. 3.1, eq. lambdat_latt)
 //   correlator  C(x0) = <q(x0) q(0) delta_Q> / <delta_Q> with the slice charge
 //        q(x0) of sec. 4 (eq. qcorr), averaged over the origin
+//   susceptibility  chi = <Q^2> / V over all configurations (sec. 4.2)
 // Errors are delete-one jackknife over configurations.
 #include <cmath>
 #include <string>
@@ -137,6 +138,27 @@ tgf_status tgf_charge_correlator(const double *q, const double *Q, int32_t n, in
                 for (double j : jk) v += (j - m) * (j - m);
                 err[x] = std::sqrt((double)(jk.size() - 1) / jk.size() * v);
             }
+        }
+    }
+    return TGF_OK;
+}
+
+tgf_status tgf_susceptibility(const double *Q, int32_t n, double V, double *chi, double *err) {
+    if (!Q || !chi || n < 1 || !(V > 0)) return bad(TGF_E_INVAL, "bad argument");
+    double s = 0;
+    for (int k = 0; k < n; k++) s += Q[k] * Q[k];
+    *chi = s / n / V;
+    if (err) {
+        if (n < 2) {
+            *err = NAN;
+        } else {
+            // delete-one estimates (s - Q_k^2) / ((n - 1) V); their mean is chi
+            double v = 0;
+            for (int k = 0; k < n; k++) {
+                const double j = (s - Q[k] * Q[k]) / (n - 1) / V - *chi;
+                v += j * j;
+            }
+            *err = std::sqrt((double)(n - 1) / n * v);
         }
     }
     return TGF_OK;

@@ -131,6 +131,9 @@ _sig = {
                                     ctypes.POINTER(ctypes.c_double), _I, _I, _I,
                                     ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]),
+    "tgf_susceptibility": (_st, [ctypes.POINTER(ctypes.c_double), _I, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]),
     "tgf_stats_last_error": (ctypes.c_char_p, []),
     "tgf_last_error": (ctypes.c_char_p, []),
     "tgf_destroy": (None, [_P]),
@@ -360,6 +363,16 @@ def charge_correlator(q, Q):
     E = np.zeros(T)
     _check_stats(tgf_charge_correlator(_dptr(q), _dptr(Q), n, T, T, _dptr(C), _dptr(E)))
     return C, E
+
+
+def susceptibility(Q, V):
+    """chi = <Q^2>/V and its jackknife error from total charges Q[n_cfg]."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    chi = ctypes.c_double()
+    err = ctypes.c_double()
+    _check_stats(tgf_susceptibility(_dptr(Q), len(Q), float(V), ctypes.byref(chi),
+                                    ctypes.byref(err)))
+    return chi.value, err.value
 
 
 def variant_names():

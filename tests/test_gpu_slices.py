@@ -60,3 +60,7 @@ def test_coupling_end_to_end():
     assert lam == pytest.approx(lo, rel=1e-11)
     C, _ = tgf.charge_correlator(qs, Q)
     assert np.isfinite(C).all()
+    V = float(np.prod(dims))
+    chi, _ = tgf.susceptibility(Q, V)
+    chi_o, _ = stats.susceptibility(rQ, V)
+    assert chi == pytest.approx(chi_o, rel=1e-9, abs=1e-18)

@@ -104,6 +104,25 @@ def test_library_coupling_and_correlator():
     assert np.allclose(C, Co, rtol=1e-12, atol=1e-15) and np.allclose(E, Eo, rtol=1e-9)
 
 
+def test_susceptibility_pins():
+    """chi = <Q^2>/V; the delete-one jackknife of a mean is the standard
+    error of that mean, s(Q^2)/sqrt(n) with the n-1 sample deviation."""
+    V = 4 * 4 * 12 * 12
+    chi, err = stats.susceptibility([1.0, -1.0] * 10, V)
+    assert chi == pytest.approx(1.0 / V, rel=1e-15) and err == pytest.approx(0.0, abs=1e-18)
+    rng = np.random.default_rng(11)
+    Q = rng.normal(0, 1.3, size=40)
+    chi, err = stats.susceptibility(Q, V)
+    assert chi == pytest.approx(np.mean(Q ** 2) / V, rel=1e-14)
+    assert err == pytest.approx(np.std(Q ** 2, ddof=1) / np.sqrt(len(Q)) / V, rel=1e-10)
+    chi_l, err_l = tgf.susceptibility(Q, V)
+    assert chi_l == pytest.approx(chi, rel=1e-14) and err_l == pytest.approx(err, rel=1e-10)
+    with pytest.raises(tgf.TGFError):
+        tgf.susceptibility(Q, 0.0)
+    with pytest.raises(tgf.TGFError):
+        tgf.susceptibility([], V)
+
+
 def test_library_stats_errors():
     with pytest.raises(tgf.TGFError) as e:
         tgf.coupling([0.1, 0.2], [1.0, 2.0], 0.3, 12)
