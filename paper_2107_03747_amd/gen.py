@@ -20,6 +20,14 @@ Generators (all seeded, all return SU(3) to rounding):
   complex Gaussian rows (Haar on the first two rows of U(3)), third row the
   conjugated cross product, which fixes det = 1 and keeps right invariance.
 
+SU(N) fields (layout ``[d3, d2, d1, d0, 4, N, N]``, 2 <= N):
+
+* ``identity_n``      -- every link = 1.
+* ``near_identity_n`` -- U = exp(i * eps * H), H = (A + A^+)/2 made traceless,
+  A with i.i.d. complex Gaussian entries (each of re, im ~ N(0, 1/2)).
+* ``haar_n``          -- QR of a complex Gaussian matrix with the phases of
+  R's diagonal moved into Q (Haar on U(N)), times det^(-1/N) (Haar on SU(N)).
+
 Random numbers come from ``torch.Generator(device).manual_seed(seed)`` so the
 same (seed, device) pair always reproduces the same field.
 """
@@ -31,7 +39,7 @@ import math
 import torch
 
 __all__ = ["lattice_shape", "identity", "near_identity", "haar", "su3_haar",
-           "gell_mann"]
+           "gell_mann", "identity_n", "near_identity_n", "haar_n"]
 
 
 def lattice_shape(dims):
@@ -113,3 +121,46 @@ def haar(dims, seed, device="cpu", chunk=1 << 22):
         e = min(n, s + chunk)
         out[s:e] = su3_haar(e - s, None, device, generator=g)
     return out.reshape(shape + (3, 3))
+
+
+def identity_n(dims, N, device="cpu"):
+    shape = lattice_shape(dims) + (4,)
+    eye = torch.eye(int(N), dtype=torch.complex128, device=device)
+    return eye.expand(shape + (int(N), int(N))).contiguous()
+
+
+def near_identity_n(dims, N, eps, seed, device="cpu", chunk=1 << 20):
+    """SU(N): U = exp(i*eps*H) per link, H a Gaussian traceless Hermitian matrix."""
+    N = int(N)
+    shape = lattice_shape(dims) + (4,)
+    n = math.prod(shape)
+    g = _gen(seed, device)
+    out = torch.empty(n, N, N, dtype=torch.complex128, device=device)
+    eye = torch.eye(N, dtype=torch.complex128, device=device)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        a = torch.randn(e - s, N, N, 2, dtype=torch.float64, device=device, generator=g)
+        A = torch.view_as_complex(a) * math.sqrt(0.5)
+        H = 0.5 * (A + A.conj().transpose(-1, -2))
+        H = H - (torch.diagonal(H, dim1=-2, dim2=-1).sum(-1) / N)[:, None, None] * eye
+        out[s:e] = torch.linalg.matrix_exp(1j * float(eps) * H)
+    return out.reshape(shape + (N, N))
+
+
+def haar_n(dims, N, seed, device="cpu", chunk=1 << 20):
+    """Haar-random SU(N) hot start."""
+    N = int(N)
+    shape = lattice_shape(dims) + (4,)
+    n = math.prod(shape)
+    g = _gen(seed, device)
+    out = torch.empty(n, N, N, dtype=torch.complex128, device=device)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        z = torch.randn(e - s, N, N, 2, dtype=torch.float64, device=device, generator=g)
+        Z = torch.view_as_complex(z)
+        Q, R = torch.linalg.qr(Z)
+        d = torch.diagonal(R, dim1=-2, dim2=-1)
+        Q = Q * (d / d.abs())[:, None, :]
+        det = torch.linalg.det(Q)
+        out[s:e] = Q * (det ** (-1.0 / N))[:, None, None]
+    return out.reshape(shape + (N, N))

@@ -9,7 +9,7 @@ from without reusing any of its staple algebra.
 
 import numpy as np
 
-from fields import OMEGA, coords, su3_generators
+from fields import coords, su3_generators
 
 
 def _dag(x):
@@ -22,6 +22,9 @@ def _shift(A, mu):
 
 
 def action(U, dims, twist=(1, 0, 0, 0, 0, 0), base=(0, 0, 0, 0)):
+    """s = sum_n sum_{mu<nu} Re Tr[1 - Z^* P] for SU(N), N = U.shape[-1];
+    Z = exp(2 pi i n_{mu nu} / N) on the twist site of each plane."""
+    N = U.shape[-1]
     n = coords(dims)
     s = 0.0
     k = 0
@@ -31,28 +34,30 @@ def action(U, dims, twist=(1, 0, 0, 0, 0, 0), base=(0, 0, 0, 0)):
                 @ _dag(_shift(U[..., mu, :, :], nu)) @ _dag(U[..., nu, :, :])
             tr = np.trace(P, axis1=-2, axis2=-1)
             z = np.ones(tr.shape, complex)
-            if twist[k] % 3:
+            if twist[k] % N:
                 on = (n[mu] == base[mu]) & (n[nu] == base[nu])
-                z[on] = OMEGA ** (twist[k] % 3)
-            s += np.sum(3.0 - np.real(np.conj(z) * tr))
+                z[on] = np.exp(2j * np.pi * (twist[k] % N) / N)
+            s += np.sum(N - np.real(np.conj(z) * tr))
             k += 1
     return s
 
 
 def expm_small(A, terms=30):
-    out = np.eye(3, dtype=complex)
-    term = np.eye(3, dtype=complex)
+    N = A.shape[-1]
+    out = np.eye(N, dtype=complex)
+    term = np.eye(N, dtype=complex)
     for k in range(1, terms):
         term = term @ A / k
         out = out + term
     return out
 
 
-def fd_force_components(U, dims, site, mu, twist=(1, 0, 0, 0, 0, 0), h=1e-4):
-    """d/ds s(exp(s T^a) U_mu(site)) at s = 0 for a = 1..8 (central differences)."""
-    T = su3_generators()
-    d = np.zeros(8)
-    for a in range(8):
+def fd_force_components(U, dims, site, mu, twist=(1, 0, 0, 0, 0, 0), h=1e-4, T=None):
+    """d/ds s(exp(s T^a) U_mu(site)) at s = 0 for every generator T^a
+    (central differences); T defaults to the SU(3) basis."""
+    T = su3_generators() if T is None else T
+    d = np.zeros(len(T))
+    for a in range(len(T)):
         vals = []
         for sgn in (+1, -1):
             V = U.copy()

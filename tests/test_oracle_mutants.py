@@ -4,8 +4,10 @@ Each case plants one mistake in a scratch copy of the oracle's C source (a
 twist factor conjugated or moved, a leaf mis-oriented, an RK3 coefficient, a
 normalisation, a sign, a neighbour index, the schedule; for the Monte Carlo a
 subgroup vector, the heat-bath coupling, an acceptance test, the direction
-draw, the checkerboard, the SU(2) embedding), rebuilds it, and requires the
-pin suite of that part (tests/test_oracle_pins.py, tests/test_oracle_mc.py)
+draw, the checkerboard, the SU(2) embedding; for SU(N) the twist phase, the
+trace part, the normalisations, a staple factor, the exponential, RK3, the
+twist modulus), rebuilds it, and requires the pin suite of that part
+(tests/test_oracle_pins.py, tests/test_oracle_mc.py, tests/test_oracle_sun.py)
 to fail.  CPU only; the real oracle is untouched.
 """
 
@@ -63,13 +65,29 @@ MC_MUTANTS = [
     ("staple not updated between subgroups", "rows_mul(&W, a, b, A);", "(void)W;"),
 ]
 
+# SU(N) mistakes (oracle/sun_oracle.c), caught by tests/test_oracle_sun.py
+SUN_MUTANTS = [
+    ("SU(N) twist phase with N = 3", "cexp(I * (2.0 * PI * L->tw[mu][nu] / L->n))",
+     "cexp(I * (2.0 * PI * L->tw[mu][nu] / 3.0))"),
+    ("SU(N) trace part 1/3", "cplx t = z_tr(n, &r) / (double)n;", "cplx t = z_tr(n, &r) / 3.0;"),
+    ("SU(N) plaquette normalisation", "out[1] = psum(d + 2, V, 4) / (6.0 * L->n * V);",
+     "out[1] = psum(d + 2, V, 4) / (18.0 * V);"),
+    ("SU(N) action constant", "s += n - re;", "s += 3 - re;"),
+    ("SU(N) lower staple factor conjugated", "z_axpy(n, zf(L, imn, mu, nu), &lo, &om);",
+     "z_axpy(n, conj(zf(L, imn, mu, nu)), &lo, &om);"),
+    ("SU(N) exponential truncated", "for (int k = 1; k <= 20; k++) {", "for (int k = 1; k <= 3; k++) {"),
+    ("SU(N) RK3 17/36 -> 17/9", "{-17.0 / 36.0, 8.0 / 9.0, 0}", "{-17.0 / 9.0, 8.0 / 9.0, 0}"),
+    ("SU(N) twist taken mod 3", "int t = twist6 ? ((twist6[k] % nc) + nc) % nc : 0;",
+     "int t = twist6 ? ((twist6[k] % 3) + 3) % 3 : 0;"),
+]
 
-def _run_mutant(tmp_path, name, old, new, pins):
+
+def _run_mutant(tmp_path, name, old, new, pins, source="tgf_oracle.c"):
     for sub in ("oracle", "tests", "paper_2107_03747_amd"):
         shutil.copytree(os.path.join(ROOT, sub), tmp_path / sub,
                         ignore=shutil.ignore_patterns("*.so", "*.so.tmp", "__pycache__"))
     shutil.copy(os.path.join(ROOT, "pytest.ini"), tmp_path)
-    src = tmp_path / "oracle" / "tgf_oracle.c"
+    src = tmp_path / "oracle" / source
     text = src.read_text()
     assert text.count(old) >= 1, f"mutation site for '{name}' not found"
     src.write_text(text.replace(old, new, 1))
@@ -87,3 +105,8 @@ def test_pins_catch_planted_mistake(tmp_path, name, old, new):
 @pytest.mark.parametrize("name,old,new", MC_MUTANTS, ids=[m[0] for m in MC_MUTANTS])
 def test_mc_pins_catch_planted_mistake(tmp_path, name, old, new):
     _run_mutant(tmp_path, name, old, new, "tests/test_oracle_mc.py")
+
+
+@pytest.mark.parametrize("name,old,new", SUN_MUTANTS, ids=[m[0] for m in SUN_MUTANTS])
+def test_sun_pins_catch_planted_mistake(tmp_path, name, old, new):
+    _run_mutant(tmp_path, name, old, new, "tests/test_oracle_sun.py", source="sun_oracle.c")

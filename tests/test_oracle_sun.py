@@ -1,0 +1,205 @@
+"""Pins of the SU(N) oracle (oracle/sun_oracle.c) against facts fixed outside
+it: the SU(3) oracle (itself pinned by tests/test_oracle_pins.py) at N = 3,
+scipy's expm, the twist algebra Gamma_1 Gamma_2 = exp(2 pi i k/N) Gamma_2
+Gamma_1 of sec. 1 (zero-action twist eaters for every coprime k), closed
+forms of abelian fields embedded in SU(N), finite differences of an
+independent numpy action, gauge invariance and the group structure of the
+flow.  The TGF geometry is l^2 x (N l)^2 (sec. 1); the action, clover and
+charge are those of sec. 3.1 with N colours.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import brute
+import fields
+import fields_n
+import oracle
+from paper_2107_03747_amd import gen
+
+TW = oracle.PAPER_TWIST
+NOTW = (0, 0, 0, 0, 0, 0)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+# ----------------------------------------------------------------------------
+# N = 3 reduces to the SU(3) oracle
+
+@pytest.mark.parametrize("dims,twist", [((4, 4, 6, 6), TW), ((3, 4, 5, 4), (1, 2, 0, 1, 0, 2)),
+                                        ((2, 2, 2, 2), NOTW)])
+def test_n3_equals_su3_oracle(dims, twist):
+    U = gen.near_identity(dims, 0.7, seed=3).numpy().copy()
+    a, b = oracle.measure(U, dims, twist), oracle.sun_measure(U, dims, twist)
+    for k in a:
+        assert abs(a[k] - b[k]) <= 1e-13 * max(1.0, abs(a[k]))
+    assert np.abs(oracle.force(U, dims, twist) - oracle.sun_force(U, dims, twist)).max() < 1e-14
+    V1, V2 = U.copy(), U.copy()
+    r1 = oracle.flow(V1, dims, 0.02, 0.1, 0.05, twist=twist)
+    r2 = oracle.sun_flow(V2, dims, 0.02, 0.1, 0.05, twist=twist)
+    assert r1.shape == r2.shape
+    assert np.abs(r1 - r2).max() < 1e-12
+    assert np.abs(V1 - V2).max() < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# exponential vs scipy
+
+@pytest.mark.parametrize("N", [2, 4, 5, 8])
+@pytest.mark.parametrize("scale", [1e-3, 0.4, 3.0, 10.0])
+def test_expm_matches_scipy(N, scale):
+    rng = np.random.default_rng(N * 100 + int(scale * 10))
+    A = rng.normal(size=(N, N)) + 1j * rng.normal(size=(N, N))
+    X = 0.5 * (A - A.conj().T)
+    X -= np.trace(X) / N * np.eye(N)
+    X *= scale / np.linalg.norm(X)
+    E = oracle.sun_expm(X)
+    assert np.abs(E - scipy.linalg.expm(X)).max() < 1e-13 * max(1.0, scale)
+
+
+# ----------------------------------------------------------------------------
+# twist eaters: Gamma_a = P^k, Gamma_b = S (clock and shift) satisfy the twist
+# algebra with Z = exp(2 pi i k/N); the field has zero action and zero force
+
+@pytest.mark.parametrize("N,k", [(2, 1), (4, 1), (4, 3), (5, 2), (6, 5), (8, 3)])
+def test_twist_eater_zero_action(N, k):
+    Ga, Gb = fields_n.twist_matrices_n(N, k)
+    w = np.exp(2j * np.pi * k / N)
+    assert np.abs(Ga @ Gb - w * Gb @ Ga).max() < 1e-14
+    dims = (2, 2, 4, 3)
+    U = fields_n.twist_eater_n(dims, N, k)
+    twist = (k, 0, 0, 0, 0, 0)
+    m = oracle.sun_measure(U, dims, twist)
+    assert abs(m["plaq"] - 1) < 1e-14 and abs(m["action"]) < 1e-11
+    assert abs(m["E"]) < 1e-14 and abs(m["Q"]) < 1e-14
+    assert np.abs(oracle.sun_force(U, dims, twist)).max() < 1e-13
+    # the same field in the box twisted by -k is not a vacuum (for N > 2)
+    if (2 * k) % N:
+        m2 = oracle.sun_measure(U, dims, ((N - k) % N, 0, 0, 0, 0, 0))
+        assert m2["action"] > 0.1
+    # and it is a fixed point of the flow
+    V = U.copy()
+    oracle.sun_flow(V, dims, 0.05, 0.1, 0.0, twist=twist)
+    assert np.abs(V - U).max() < 1e-13
+
+
+def test_unit_links_in_twisted_box():
+    """Unit links: only the twisted plaquettes (one per (n2, n3)) contribute,
+    each Re Tr[1 - Z^*] = N (1 - cos(2 pi k/N))."""
+    for N, k in ((2, 1), (4, 1), (5, 2)):
+        dims = (3, 3, 4, 5)
+        U = fields_n.identity_n(dims, N)
+        m = oracle.sun_measure(U, dims, (k, 0, 0, 0, 0, 0))
+        assert rel(m["action"], dims[2] * dims[3] * N * (1 - math.cos(2 * math.pi * k / N))) < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# constant abelian flux in the first SU(2) block: closed forms
+
+@pytest.mark.parametrize("N", [2, 4, 6])
+def test_flux_closed_form(N):
+    dims = (6, 4, 6, 8)
+    U, p01, p23 = fields_n.flux_field_n(dims, N, 2, -1)
+    V = np.prod(dims)
+    m = oracle.sun_measure(U, dims, NOTW)
+    assert rel(m["E"], 2 * np.sin(p01) ** 2 + 2 * np.sin(p23) ** 2) < 1e-13
+    assert rel(m["Q"], V * 2 * np.sin(p01) * np.sin(p23) / (4 * np.pi ** 2)) < 1e-12
+    plaq = (4 * N + (2 * np.cos(p01) + N - 2) + (2 * np.cos(p23) + N - 2)) / (6 * N)
+    assert abs(m["plaq"] - plaq) < 1e-14
+    assert np.abs(oracle.sun_force(U, dims, NOTW)).max() < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# single Fourier mode: force normalisation and the RK3 stability polynomial
+
+@pytest.mark.parametrize("N,rho,pn", [(2, 3, (1, 1, 1, 0)), (4, 0, (0, 1, 2, 3)),
+                                      (5, 2, (1, 0, 0, 2))])
+def test_single_mode_energy_and_decay(N, rho, pn):
+    dims = (4, 4, 8, 8)
+    p = np.array([2 * np.pi * pn[m] / dims[m] for m in range(4)])
+    alpha = 1e-3
+    U = fields_n.single_mode_n(dims, N, alpha, p, rho)
+    E0 = 0.25 * alpha ** 2 * sum(np.sin(p[m]) ** 2 for m in range(4) if m != rho)
+    eps = 0.04
+    rows = oracle.sun_flow(U, dims, eps, 0.2, eps, twist=NOTW)
+    assert rel(rows[0, 1], E0) < 1e-5
+    phat2 = sum(4 * np.sin(p[m] / 2) ** 2 for m in range(4))
+    z = -eps * phat2
+    R = 1 + z + z * z / 2 + z ** 3 / 6
+    for r in rows:
+        k = round(r[0] / eps)
+        assert rel(r[1], E0 * R ** (2 * k)) < 1e-5
+
+
+# ----------------------------------------------------------------------------
+# force vs finite differences of an independent numpy action
+
+@pytest.mark.parametrize("N,dims,twist", [(2, (2, 2, 3, 2), TW), (4, (2, 2, 2, 3), TW),
+                                          (4, (3, 2, 2, 2), (1, 0, 3, 2, 0, 1)),
+                                          (5, (2, 2, 2, 2), (2, 0, 0, 0, 0, 0))])
+def test_force_matches_action_derivative(N, dims, twist):
+    U = gen.haar_n(dims, N, seed=21).numpy().copy()
+    F = oracle.sun_force(U, dims, twist)
+    T = fields_n.su_n_generators(N)
+    assert rel(brute.action(U, dims, twist), oracle.sun_measure(U, dims, twist)["action"]) < 1e-12
+    d0, d1, d2, d3 = dims
+    rng = np.random.default_rng(N)
+    sites = [(0, 0, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1), (1, 1, 0, 0)]
+    sites += [tuple(int(rng.integers(d)) for d in (d3, d2, d1, d0)) for _ in range(2)]
+    for site in sites:
+        for mu in range(4):
+            fd = brute.fd_force_components(U, dims, site, mu, twist, T=T)
+            an = np.array([np.trace(T[a] @ F[site + (mu,)]).real for a in range(len(T))])
+            assert np.abs(fd - an).max() < 1e-7, (site, mu)
+    assert np.abs(F + np.conj(np.swapaxes(F, -1, -2))).max() < 1e-14
+    assert np.abs(np.trace(F, axis1=-2, axis2=-1)).max() < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# gauge invariance, group structure, monotone action
+
+def test_gauge_invariance_and_covariance():
+    N, dims = 4, (4, 4, 4, 4)
+    U = gen.near_identity_n(dims, N, 0.5, seed=31).numpy().copy()
+    Lam = gen.haar_n(dims, N, seed=32).numpy()[..., 0, :, :].copy()
+    Ug = fields.gauge_transform(U, Lam)
+    a = oracle.sun_flow(U, dims, 0.02, 0.06, 0.02, twist=TW)
+    b = oracle.sun_flow(Ug, dims, 0.02, 0.06, 0.02, twist=TW)
+    assert np.allclose(a[:, 1], b[:, 1], rtol=1e-12, atol=0)
+    assert np.allclose(a[:, 3], b[:, 3], rtol=1e-14, atol=0)
+    assert np.allclose(a[:, 4], b[:, 4], rtol=0, atol=1e-12)
+    assert np.abs(fields.gauge_transform(U, Lam) - Ug).max() < 1e-12
+
+
+@pytest.mark.parametrize("N", [2, 5])
+def test_flow_stays_on_group_and_action_decreases(N):
+    dims = (2, 2, 2 * N, 2 * N)
+    U = gen.haar_n(dims, N, seed=7).numpy().copy()
+    rows = oracle.sun_flow(U, dims, 0.02, 0.2, 0.02, twist=TW)
+    du, dd = fields_n.unitarity_defect_n(U)
+    assert du < 1e-13 and dd < 1e-13
+    assert np.all(np.diff(rows[:, 5]) < 0)
+
+
+def test_rk3_third_order():
+    N, dims = 4, (2, 2, 4, 4)
+    U = gen.near_identity_n(dims, N, 0.8, seed=9).numpy().copy()
+    ref = U.copy()
+    oracle.sun_flow(ref, dims, 0.0025, 0.2, 0.0, twist=TW)
+    errs = []
+    for eps in (0.04, 0.02, 0.01):
+        V = U.copy()
+        oracle.sun_flow(V, dims, eps, 0.2, 0.0, twist=TW)
+        errs.append(np.abs(V - ref).max())
+    assert 6 < errs[0] / errs[1] < 10 and 6 < errs[1] / errs[2] < 10
+
+
+def test_rejects_bad_n():
+    U = np.zeros((2, 2, 2, 2, 4, 9, 9), complex)
+    with pytest.raises(RuntimeError):
+        oracle.sun_measure(U, (2, 2, 2, 2))
