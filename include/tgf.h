@@ -127,6 +127,28 @@ size_t tgf_workspace_bytes(int32_t n_cfg, const tgf_geom *geoms, tgf_storage st)
 tgf_status tgf_create(tgf_ctx **out, int32_t n_cfg, const tgf_geom *geoms, tgf_storage st,
                       void *workspace_dev, size_t workspace_bytes, void *hip_stream);
 
+/* General SU(N), 2 <= nc <= 8 (sec. 1: the TGF scheme is defined for SU(N) on
+ * an l^2 x (N l)^2 box whose short plane is twisted by Z_12 = exp(2 pi i k/N),
+ * k coprime to N; the action, clover and charge of sec. 3.1 with N colours).
+ * A context made by tgf_create_sun runs the general-N kernels (for nc = 3 as
+ * well; tgf_create is the SU(3)-specialised path) and accepts every call
+ * above and below with these differences:
+ *   - storage must be TGF_F64_FULL (TGF_E_UNSUPPORTED otherwise);
+ *   - links are complex128 [d3][d2][d1][d0][4][nc][nc] (row-major nc x nc);
+ *     tgf_load_links* require SU(nc) within 1e-10 (TGF_E_NOT_SU3 otherwise);
+ *   - twist entries n_{mu nu} are in 0..nc-1, Z_{mu nu} = exp(2 pi i n/nc);
+ *   - sites per configuration <= 2^28 / nc^2 - 256;
+ *   - plaq = (1/(6 nc V)) sum_n sum_{mu<nu} Re Tr[Z^* P], action =
+ *     sum_n sum_{mu<nu} Re Tr[1 - Z^* P], force -P_ah with the trace/nc part;
+ *   - one stage kernel: tgf_autotune does nothing, tgf_set_variant accepts
+ *     only -1; tgf_mc and tgf_slice_charge return TGF_E_UNSUPPORTED.
+ * tgf_workspace_bytes_sun returns 0 on invalid arguments. */
+size_t tgf_workspace_bytes_sun(int32_t nc, int32_t n_cfg, const tgf_geom *geoms,
+                               tgf_storage st);
+tgf_status tgf_create_sun(tgf_ctx **out, int32_t nc, int32_t n_cfg, const tgf_geom *geoms,
+                          tgf_storage st, void *workspace_dev, size_t workspace_bytes,
+                          void *hip_stream);
+
 /* Copy links of configuration cfg from canonical device memory into the
  * context's storage and set its flow time to t0.  The input is checked:
  * max |U U^+ - 1| and |det U - 1| above 1e-10 (or any non-finite entry)

@@ -543,7 +543,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const CfgDesc *__restrict
                                                        const MeasSlot *__restrict__ slots,
                                                        const double *__restrict__ partials,
                                                        double *__restrict__ rows, int n_cfg_total,
-                                                       int *__restrict__ flag) {
+                                                       int *__restrict__ flag, int nc) {
     const int ci = blockIdx.x;
     const MeasSlot sl = slots[ci];
     if (sl.row < 0) return;
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const CfgDesc *__restrict
         r[0] = sl.t;
         r[1] = E;
         r[2] = sl.t * sl.t * E;
-        r[3] = tot[2] / (18.0 * V);
+        r[3] = tot[2] / (6.0 * nc * V);
         r[4] = tot[1];
         r[5] = tot[3];
         if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2]) || !isfinite(tot[3]))
@@ -777,10 +777,10 @@ hipError_t launch_measure(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
 
 hipError_t launch_finalize(hipStream_t s, const CfgDesc *cfgs, const int *tile_start, int n_cfg,
                            const MeasSlot *slots, const double *partials, double *rows,
-                           int n_cfg_total, int *flag) {
+                           int n_cfg_total, int *flag, int nc) {
     if (n_cfg <= 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_kernel, dim3(n_cfg), dim3(256), 0, s, cfgs, tile_start, slots,
-                       partials, rows, n_cfg_total, flag);
+                       partials, rows, n_cfg_total, flag, nc);
     return hipGetLastError();
 }
 
@@ -834,6 +834,10 @@ hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void 
                            stride, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    return launch_check_final(s, partials, ntiles, out);
+}
+
+hipError_t launch_check_final(hipStream_t s, const double *partials, int ntiles, double *out) {
     hipLaunchKernelGGL(check_final_kernel, dim3(1), dim3(256), 0, s, partials, ntiles, out);
     return hipGetLastError();
 }

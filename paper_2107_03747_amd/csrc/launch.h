@@ -37,9 +37,10 @@ hipError_t launch_measure(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
                           const int *tile_start, int n_cfg, int n_tiles, const MeasSlot *slots,
                           double *partials, int buf_sel);
 
+// nc: colours (the plaquette is normalised by 6 nc V)
 hipError_t launch_finalize(hipStream_t s, const CfgDesc *cfgs, const int *tile_start, int n_cfg,
                            const MeasSlot *slots, const double *partials, double *rows,
-                           int n_cfg_total, int *flag);
+                           int n_cfg_total, int *flag, int nc);
 
 // canonical complex128 [V][4][3][3] <-> storage buffer W (of config c)
 hipError_t launch_pack(Prec p, bool c12, hipStream_t s, const void *src, void *W, int V,
@@ -66,6 +67,21 @@ hipError_t launch_slice_charge(Prec p, bool c12, hipStream_t s, const CfgDesc *c
 hipError_t launch_mc(hipStream_t s, const CfgDesc *cfgs, const int *tile_start, int n_cfg,
                      int n_tiles, int mu, int par, int heatbath, double beta, uint64_t seed,
                      uint32_t sweep);
+
+// max over ntiles pairs of defects in partials -> out[2]
+hipError_t launch_check_final(hipStream_t s, const double *partials, int ntiles, double *out);
+
+// General SU(N), FP64 full storage [mu][N^2][stride], 2 <= nc <= 8 (sun.hip).
+// Same tile table, ping-pong and partials conventions as the SU(3) launchers.
+hipError_t launch_stage_sun(int nc, hipStream_t s, const CfgDesc *cfgs, const int *tile_start,
+                            int n_act, int n_tiles, int step, int stage, double eps);
+hipError_t launch_measure_sun(int nc, hipStream_t s, const CfgDesc *cfgs, const int *tile_start,
+                              int n_cfg, int n_tiles, const MeasSlot *slots, double *partials,
+                              int buf_sel);
+hipError_t launch_pack_sun(int nc, hipStream_t s, const void *src, void *W, int V, int stride);
+hipError_t launch_unpack_sun(int nc, hipStream_t s, const void *W, void *dst, int V, int stride);
+hipError_t launch_check_sun(int nc, bool canon, hipStream_t s, const void *src, int V, int stride,
+                            double *partials, double *out);
 
 hipError_t launch_fill_int(hipStream_t s, int *dst, int n, int value);
 hipError_t launch_copy(hipStream_t s, void *dst, const void *src, size_t bytes);

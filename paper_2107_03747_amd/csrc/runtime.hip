@@ -67,7 +67,8 @@ struct Layout {
 int ne_of(tgf_storage st) { return st == TGF_F32_C12 ? 6 : 9; }
 size_t cx_bytes(tgf_storage st) { return st == TGF_F64_FULL ? 16 : 8; }
 
-tgf_status validate_geoms(int32_t n_cfg, const tgf_geom *g) {
+// nc: colours; general: the SU(N) storage (N^2 entries per link)
+tgf_status validate_geoms(int32_t n_cfg, const tgf_geom *g, int nc = 3, bool general = false) {
     if (n_cfg <= 0) return fail(TGF_E_INVAL, "n_cfg must be positive");
     if (!g) return fail(TGF_E_INVAL, "geoms is NULL");
     for (int c = 0; c < n_cfg; c++) {
@@ -77,18 +78,22 @@ tgf_status validate_geoms(int32_t n_cfg, const tgf_geom *g) {
                 return fail(TGF_E_INVAL, "config " + std::to_string(c) + ": dims must be >= 2");
             V *= g[c].dims[m];
         }
-        // every per-lane byte offset into an entry plane must fit in 32 bits
-        if (V > (1LL << 28) - 256)
+        // every per-lane byte offset into an entry plane (into the N^2 planes of
+        // one direction for the SU(N) storage) must fit in 32 bits
+        const long long cap = general ? (1LL << 28) / (nc * nc) - 256 : (1LL << 28) - 256;
+        if (V > cap)
             return fail(TGF_E_INVAL, "config " + std::to_string(c) + ": lattice too large");
         for (int k = 0; k < 6; k++)
-            if (g[c].twist[k] < 0 || g[c].twist[k] > 2)
-                return fail(TGF_E_INVAL,
-                            "config " + std::to_string(c) + ": twist entries must be 0, 1 or 2");
+            if (g[c].twist[k] < 0 || g[c].twist[k] >= nc)
+                return fail(TGF_E_INVAL, "config " + std::to_string(c) +
+                                             ": twist entries must be in 0.." +
+                                             std::to_string(nc - 1));
     }
     return TGF_OK;
 }
 
-Layout make_layout(int32_t n_cfg, const tgf_geom *g, tgf_storage st) {
+Layout make_layout(int32_t n_cfg, const tgf_geom *g, tgf_storage st, int nc = 3,
+                   bool general = false) {
     Layout L;
     L.cfg.resize(n_cfg);
     int tiles = 0;
@@ -114,12 +119,13 @@ Layout make_layout(int32_t n_cfg, const tgf_geom *g, tgf_storage st) {
     L.off_meas = o;     o = align_up(o + sizeof(MeasSlot) * (size_t)(kMaxRows + 1) * n_cfg, 256);
     L.off_cfg0 = o;
     const size_t e = cx_bytes(st);
-    const int NE = ne_of(st);
+    const int NE = general ? nc * nc : ne_of(st);
     for (int c = 0; c < n_cfg; c++) {
         CfgHost &h = L.cfg[c];
         size_t wb = e * 4 * NE * (size_t)h.stride;
-        size_t xb = e * 4 * 4 * (size_t)h.stride;
-        size_t ab = e * 6 * 4 * (size_t)h.stride;
+        // SU(N): X is a full N x N matrix per link and there is no A buffer
+        size_t xb = e * 4 * (general ? NE : 4) * (size_t)h.stride;
+        size_t ab = general ? 0 : e * 6 * 4 * (size_t)h.stride;
         h.offW[0] = o; o = align_up(o + wb, 256);
         h.offW[1] = o; o = align_up(o + wb, 256);
         h.offX = o;    o = align_up(o + xb, 256);
@@ -152,6 +158,8 @@ struct tgf_ctx {
     size_t ws_bytes;
     Layout L;
     int variant = -1;
+    int nc = 3;              // colours
+    bool general = false;    // SU(N) kernels (tgf_create_sun), for any N including 3
     // host pinned staging
     char *h_stage = nullptr;
     size_t h_stage_bytes = 0;
@@ -172,6 +180,8 @@ struct tgf_ctx {
     MeasSlot *d_meas() { return (MeasSlot *)(ws + L.off_meas); }
     Prec prec() const { return st == TGF_F64_FULL ? P_F64 : P_F32; }
     bool c12() const { return st == TGF_F32_C12; }
+    int ne() const { return general ? nc * nc : (st == TGF_F32_C12 ? 6 : 9); }
+    int x_entries() const { return general ? nc * nc : 4; }
     int effective_variant() const {
         if (variant >= 0) return variant;
         return st == TGF_F64_FULL ? V_LINK : V_SITE;
@@ -249,17 +259,24 @@ tgf_status run_launches(tgf_ctx *c, const std::vector<Launch> &ls, double eps, b
         switch (l.kind) {
             case 0:
             case 4:
+                if (c->general)
+                    return launch_stage_sun(c->nc, s, c->d_desc(), c->d_tiles(), l.n_act, l.grid,
+                                            l.step, l.stage, eps);
                 return launch_stage(variant, l.kind == 0 ? 1 : 0, c->prec(), c->c12(), s,
                                     c->d_desc(), c->d_tiles(), l.n_act, l.grid, l.step, l.stage,
                                     eps, l.reunit);
             case 1:
+                if (c->general)
+                    return launch_measure_sun(c->nc, s, c->d_desc(), c->d_tiles(), l.n_act, l.grid,
+                                              c->d_meas() + (size_t)l.event * c->n_cfg,
+                                              c->d_partials(), l.step);
                 return launch_measure(c->prec(), c->c12(), s, c->d_desc(), c->d_tiles(), l.n_act,
                                       l.grid, c->d_meas() + (size_t)l.event * c->n_cfg,
                                       c->d_partials(), l.step);
             case 2:
                 return launch_finalize(s, c->d_desc(), c->d_tiles(), l.n_act,
                                        c->d_meas() + (size_t)l.event * c->n_cfg, c->d_partials(),
-                                       c->d_rows(), c->n_cfg, c->d_flag());
+                                       c->d_rows(), c->n_cfg, c->d_flag(), c->nc);
             default:
                 return launch_fill_int(s, c->d_flag(), 1, 0);
         }
@@ -327,8 +344,12 @@ tgf_status check_cfg(tgf_ctx *c, int32_t cfg) {
 // Unitarity defects of canonical (canon) or stored links of config cfg.
 tgf_status run_check(tgf_ctx *c, int cfg, const void *src, bool canon, double out[2]) {
     const CfgHost &h = c->L.cfg[cfg];
-    HIP_TRY(launch_check(c->prec(), c->c12(), canon, c->stream, src, h.V, h.stride,
-                         c->d_partials(), c->d_check()));
+    if (c->general)
+        HIP_TRY(launch_check_sun(c->nc, canon, c->stream, src, h.V, h.stride, c->d_partials(),
+                                 c->d_check()));
+    else
+        HIP_TRY(launch_check(c->prec(), c->c12(), canon, c->stream, src, h.V, h.stride,
+                             c->d_partials(), c->d_check()));
     tgf_status st = ensure_stage(c, 64);
     if (st) return st;
     HIP_TRY(hipMemcpyAsync(c->h_stage, c->d_check(), 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -388,18 +409,29 @@ size_t tgf_workspace_bytes(int32_t n_cfg, const tgf_geom *geoms, tgf_storage st)
     return make_layout(n_cfg, geoms, st).total;
 }
 
-tgf_status tgf_create(tgf_ctx **out, int32_t n_cfg, const tgf_geom *geoms, tgf_storage st,
-                      void *workspace_dev, size_t workspace_bytes, void *hip_stream) {
+size_t tgf_workspace_bytes_sun(int32_t nc, int32_t n_cfg, const tgf_geom *geoms,
+                               tgf_storage st) {
+    if (nc < 2 || nc > 8 || st != TGF_F64_FULL) return 0;
+    if (validate_geoms(n_cfg, geoms, nc, true) != TGF_OK) return 0;
+    return make_layout(n_cfg, geoms, st, nc, true).total;
+}
+
+static tgf_status create_impl(tgf_ctx **out, int nc, bool general, int32_t n_cfg,
+                              const tgf_geom *geoms, tgf_storage st, void *workspace_dev,
+                              size_t workspace_bytes, void *hip_stream) {
     g_err.clear();
     if (!out) return fail(TGF_E_INVAL, "out is NULL");
     *out = nullptr;
     if (st < TGF_F64_FULL || st > TGF_F32_C12) return fail(TGF_E_INVAL, "unknown storage");
-    tgf_status s = validate_geoms(n_cfg, geoms);
+    if (general && (nc < 2 || nc > 8)) return fail(TGF_E_INVAL, "nc must be 2..8");
+    if (general && st != TGF_F64_FULL)
+        return fail(TGF_E_UNSUPPORTED, "SU(N) contexts use TGF_F64_FULL storage");
+    tgf_status s = validate_geoms(n_cfg, geoms, nc, general);
     if (s) return s;
     if (!workspace_dev) return fail(TGF_E_INVAL, "workspace is NULL");
     if (((uintptr_t)workspace_dev) % 256)
         return fail(TGF_E_INVAL, "workspace must be 256-byte aligned");
-    Layout L = make_layout(n_cfg, geoms, st);
+    Layout L = make_layout(n_cfg, geoms, st, nc, general);
     if (workspace_bytes < L.total)
         return fail(TGF_E_SIZE, "workspace too small: need " + std::to_string(L.total) +
                                     " bytes, got " + std::to_string(workspace_bytes));
@@ -407,12 +439,27 @@ tgf_status tgf_create(tgf_ctx **out, int32_t n_cfg, const tgf_geom *geoms, tgf_s
     if (!c) return fail(TGF_E_INVAL, "out of host memory");
     c->n_cfg = n_cfg;
     c->st = st;
+    c->nc = nc;
+    c->general = general;
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char *)workspace_dev;
     c->ws_bytes = workspace_bytes;
     c->L = std::move(L);
     *out = c;
     return TGF_OK;
+}
+
+tgf_status tgf_create(tgf_ctx **out, int32_t n_cfg, const tgf_geom *geoms, tgf_storage st,
+                      void *workspace_dev, size_t workspace_bytes, void *hip_stream) {
+    return create_impl(out, 3, false, n_cfg, geoms, st, workspace_dev, workspace_bytes,
+                       hip_stream);
+}
+
+tgf_status tgf_create_sun(tgf_ctx **out, int32_t nc, int32_t n_cfg, const tgf_geom *geoms,
+                          tgf_storage st, void *workspace_dev, size_t workspace_bytes,
+                          void *hip_stream) {
+    return create_impl(out, nc, true, n_cfg, geoms, st, workspace_dev, workspace_bytes,
+                       hip_stream);
 }
 
 void tgf_destroy(tgf_ctx *c) {
@@ -433,8 +480,12 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
     // defects to its own slot of the rows region, one readback for all
     for (size_t k = 0; k < cfgs.size(); k++) {
         const CfgHost &h = c->L.cfg[cfgs[k]];
-        HIP_TRY(launch_check(c->prec(), c->c12(), true, c->stream, links[k], h.V, h.stride,
-                             c->d_partials(), c->d_rows() + 2 * k));
+        if (c->general)
+            HIP_TRY(launch_check_sun(c->nc, true, c->stream, links[k], h.V, h.stride,
+                                     c->d_partials(), c->d_rows() + 2 * k));
+        else
+            HIP_TRY(launch_check(c->prec(), c->c12(), true, c->stream, links[k], h.V, h.stride,
+                                 c->d_partials(), c->d_rows() + 2 * k));
     }
     tgf_status st0 = ensure_stage(c, sizeof(double) * 2 * cfgs.size());
     if (st0) return st0;
@@ -454,14 +505,17 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
     }
     if (bad >= 0) {
         char buf[160];
-        snprintf(buf, sizeof buf, "config %d: links not in SU(3): max|UU^+-1| = %.3g, "
-                 "max|det-1| = %.3g", bad, worst[0], worst[1]);
+        snprintf(buf, sizeof buf, "config %d: links not in SU(%d): max|UU^+-1| = %.3g, "
+                 "max|det-1| = %.3g", bad, c->nc, worst[0], worst[1]);
         return fail(TGF_E_NOT_SU3, buf);
     }
     for (size_t k = 0; k < cfgs.size(); k++) {
         CfgHost &h = c->L.cfg[cfgs[k]];
-        HIP_TRY(launch_pack(c->prec(), c->c12(), c->stream, links[k], c->ws + h.offW[0], h.V,
-                            h.stride));
+        if (c->general)
+            HIP_TRY(launch_pack_sun(c->nc, c->stream, links[k], c->ws + h.offW[0], h.V, h.stride));
+        else
+            HIP_TRY(launch_pack(c->prec(), c->c12(), c->stream, links[k], c->ws + h.offW[0], h.V,
+                                h.stride));
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (size_t k = 0; k < cfgs.size(); k++) {
@@ -501,8 +555,12 @@ tgf_status tgf_store_links(tgf_ctx *c, int32_t cfg, void *links_dev) {
     if (!links_dev) return fail(TGF_E_INVAL, "links pointer is NULL");
     CfgHost &h = c->L.cfg[cfg];
     if (!h.loaded) return fail(TGF_E_STATE, "config not loaded");
-    HIP_TRY(launch_unpack(c->prec(), c->c12(), c->stream, c->ws + h.offW[h.cur], links_dev, h.V,
-                          h.stride));
+    if (c->general)
+        HIP_TRY(launch_unpack_sun(c->nc, c->stream, c->ws + h.offW[h.cur], links_dev, h.V,
+                                  h.stride));
+    else
+        HIP_TRY(launch_unpack(c->prec(), c->c12(), c->stream, c->ws + h.offW[h.cur], links_dev,
+                              h.V, h.stride));
     return TGF_OK;
 }
 
@@ -546,10 +604,14 @@ tgf_status tgf_measure(tgf_ctx *c, tgf_obs *out_host) {
     HIP_TRY(hipMemcpyAsync(c->d_meas(), ms, sizeof(MeasSlot) * c->n_cfg, hipMemcpyHostToDevice,
                            c->stream));
     HIP_TRY(launch_fill_int(c->stream, c->d_flag(), 1, 0));
-    HIP_TRY(launch_measure(c->prec(), c->c12(), c->stream, c->d_desc(), c->d_tiles(), c->n_cfg,
-                           ts[c->n_cfg], c->d_meas(), c->d_partials(), -1));
+    if (c->general)
+        HIP_TRY(launch_measure_sun(c->nc, c->stream, c->d_desc(), c->d_tiles(), c->n_cfg,
+                                   ts[c->n_cfg], c->d_meas(), c->d_partials(), -1));
+    else
+        HIP_TRY(launch_measure(c->prec(), c->c12(), c->stream, c->d_desc(), c->d_tiles(),
+                               c->n_cfg, ts[c->n_cfg], c->d_meas(), c->d_partials(), -1));
     HIP_TRY(launch_finalize(c->stream, c->d_desc(), c->d_tiles(), c->n_cfg, c->d_meas(),
-                            c->d_partials(), c->d_rows(), c->n_cfg, c->d_flag()));
+                            c->d_partials(), c->d_rows(), c->n_cfg, c->d_flag(), c->nc));
     HIP_TRY(hipStreamSynchronize(c->stream));   // the slot upload used the staging buffer
     size_t rb = sizeof(double) * 6 * c->n_cfg;
     HIP_TRY(hipMemcpyAsync(c->h_stage, c->d_rows(), rb, hipMemcpyDeviceToHost, c->stream));
@@ -680,7 +742,7 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
     if (timing) {
         tgf_timing tm{};
         const double e = (double)cx_bytes(c->st);
-        const int NE = ne_of(c->st);
+        const int NE = c->ne();
         for (size_t k = 0; k < ls.size(); k++) {
             float ms_ = 0;
             HIP_TRY(hipEventElapsedTime(&ms_, c->events[2 * k], c->events[2 * k + 1]));
@@ -689,7 +751,8 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
             if (l.kind == 0 || l.kind == 4)
                 for (int j = 0; j < l.n_act; j++) sites += c->L.cfg[order[j]].V;
             // algorithmic bytes: every element an operation touches, once
-            const double links = 4.0 * NE * e, xs = 4.0 * 4 * e, as = 6.0 * 4 * e;
+            const double links = 4.0 * NE * e, xs = 4.0 * c->x_entries() * e,
+                         as = 6.0 * 4 * e;
             if (l.kind == 0) {
                 tm.stage_ms += ms_;
                 tm.stage_launches++;
@@ -736,6 +799,7 @@ tgf_status tgf_slice_charge(tgf_ctx *c, int32_t dir, double *q_host, int32_t max
     if (s) return s;
     if (dir < 0 || dir > 3) return fail(TGF_E_INVAL, "dir must be 0..3");
     if (!q_host) return fail(TGF_E_INVAL, "q_host is NULL");
+    if (c->general) return fail(TGF_E_UNSUPPORTED, "slice charge: SU(3) contexts only");
     size_t total = 0;
     for (int k = 0; k < c->n_cfg; k++) {
         const CfgHost &h = c->L.cfg[k];
@@ -779,6 +843,7 @@ tgf_status tgf_mc(tgf_ctx *c, double b, int32_t n_hybrid, int32_t n_or, uint64_t
     if (s) return s;
     if (c->st != TGF_F64_FULL)
         return fail(TGF_E_INVAL, "Monte Carlo needs TGF_F64_FULL storage");
+    if (c->general) return fail(TGF_E_UNSUPPORTED, "Monte Carlo: SU(3) contexts only");
     if (!std::isfinite(b) || b < 0) return fail(TGF_E_INVAL, "b must be finite and >= 0");
     if (n_hybrid < 0 || n_or < 0) return fail(TGF_E_INVAL, "n_hybrid and n_or must be >= 0");
     const uint64_t sweeps = (uint64_t)n_hybrid * (uint64_t)(1 + (int64_t)n_or);
@@ -830,6 +895,8 @@ tgf_status tgf_set_variant(tgf_ctx *c, int32_t v) {
     tgf_status s = check_ctx(c);
     if (s) return s;
     if (v < -1 || v >= V_COUNT) return fail(TGF_E_INVAL, "variant out of range");
+    if (c->general && v != -1)
+        return fail(TGF_E_UNSUPPORTED, "SU(N) contexts have a single stage kernel");
     c->variant = v;
     return TGF_OK;
 }
@@ -859,6 +926,7 @@ tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path) {
     for (int k = 0; k < c->n_cfg; k++)
         if (!c->L.cfg[k].loaded)
             return fail(TGF_E_STATE, "config " + std::to_string(k) + " not loaded");
+    if (c->general) return TGF_OK;   // one stage kernel: nothing to choose
     const std::string key = tune_key(c);
     if (cache_path) {
         std::ifstream in(cache_path);

@@ -106,6 +106,9 @@ _sig = {
     "tgf_workspace_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(tgf_geom), _st]),
     "tgf_create": (_st, [ctypes.POINTER(_P), _I, ctypes.POINTER(tgf_geom), _st, _P,
                          ctypes.c_size_t, _P]),
+    "tgf_workspace_bytes_sun": (ctypes.c_size_t, [_I, _I, ctypes.POINTER(tgf_geom), _st]),
+    "tgf_create_sun": (_st, [ctypes.POINTER(_P), _I, _I, ctypes.POINTER(tgf_geom), _st, _P,
+                             ctypes.c_size_t, _P]),
     "tgf_load_links": (_st, [_P, _I, _P, ctypes.c_double]),
     "tgf_load_links_all": (_st, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double)]),
     "tgf_store_links": (_st, [_P, _I, _P]),
@@ -186,9 +189,11 @@ class Flow:
 
     geoms:   list of dims (d0, d1, d2, d3) or (dims, twist) pairs.
     storage: "f64" (plain FP64), "f32" (FP32 full), "f32c12" (FP32 rows 0, 1).
+    nc:      None for the SU(3)-specialised kernels; 2..8 for the general SU(N)
+             kernels (FP64 storage, links [d3,d2,d1,d0,4,nc,nc], twist mod nc).
     """
 
-    def __init__(self, geoms, storage="f32c12", device="cuda", stream=None):
+    def __init__(self, geoms, storage="f32c12", device="cuda", stream=None, nc=None):
         import torch
         self.torch = torch
         self.geoms = list(geoms)
@@ -196,17 +201,28 @@ class Flow:
         self.dims = [tuple(int(x) for x in (g[0] if hasattr(g[0], "__len__") else g))
                      for g in self.geoms]
         self.storage = storage
+        self.nc = 3 if nc is None else int(nc)
+        self.general = nc is not None
         self.device = torch.device(device)
         self._g = make_geoms(self.geoms)
-        nbytes = int(tgf_workspace_bytes(self.n, self._g, STORAGES[storage]))
+        if self.general:
+            nbytes = int(tgf_workspace_bytes_sun(self.nc, self.n, self._g, STORAGES[storage]))
+        else:
+            nbytes = int(tgf_workspace_bytes(self.n, self._g, STORAGES[storage]))
         if nbytes == 0:
-            raise TGFError(TGF_E_INVAL, "invalid geometries: " + tgf_last_error().decode())
+            raise TGFError(TGF_E_INVAL, "invalid geometries, storage or nc: " +
+                           tgf_last_error().decode())
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         self._ctx = ctypes.c_void_p()
-        check(tgf_create(ctypes.byref(self._ctx), self.n, self._g, STORAGES[storage],
-                         _ptr(self.workspace), nbytes,
-                         ctypes.c_void_p(self.stream.cuda_stream)))
+        if self.general:
+            check(tgf_create_sun(ctypes.byref(self._ctx), self.nc, self.n, self._g,
+                                 STORAGES[storage], _ptr(self.workspace), nbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream)))
+        else:
+            check(tgf_create(ctypes.byref(self._ctx), self.n, self._g, STORAGES[storage],
+                             _ptr(self.workspace), nbytes,
+                             ctypes.c_void_p(self.stream.cuda_stream)))
 
     def close(self):
         if self._ctx:
@@ -222,10 +238,11 @@ class Flow:
     def _links_ok(self, cfg, links):
         t = self.torch
         d0, d1, d2, d3 = self.dims[cfg]
+        n = self.nc
         if not (links.is_cuda and links.dtype == t.complex128 and links.is_contiguous()
-                and tuple(links.shape) == (d3, d2, d1, d0, 4, 3, 3)):
+                and tuple(links.shape) == (d3, d2, d1, d0, 4, n, n)):
             raise ValueError("links must be a contiguous complex128 CUDA tensor "
-                             f"[{d3},{d2},{d1},{d0},4,3,3]")
+                             f"[{d3},{d2},{d1},{d0},4,{n},{n}]")
 
     def _sync_in(self):
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
@@ -249,8 +266,8 @@ class Flow:
         t = self.torch
         dims = self.dims[cfg]
         if out is None:
-            out = t.empty((dims[3], dims[2], dims[1], dims[0], 4, 3, 3), dtype=t.complex128,
-                          device=self.device)
+            out = t.empty((dims[3], dims[2], dims[1], dims[0], 4, self.nc, self.nc),
+                          dtype=t.complex128, device=self.device)
         self._links_ok(cfg, out)
         self._sync_in()
         check(tgf_store_links(self._ctx, int(cfg), _ptr(out)))

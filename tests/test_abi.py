@@ -138,3 +138,31 @@ def test_null_context_is_rejected():
 def test_variant_table():
     names = tgf.variant_names()
     assert names[:2] == ["site", "link"] and len(names) == tgf.tgf_variant_count()
+
+
+def test_sun_workspace_and_create_validation():
+    g = tgf.make_geoms([((4, 4, 16, 16), (3, 0, 0, 0, 0, 0))])
+    F64 = tgf.TGF_F64_FULL
+    V = 4 * 4 * 16 * 16
+    b2 = tgf.tgf_workspace_bytes_sun(2, 1, tgf.make_geoms([(4, 4, 16, 16)]), F64)
+    for nc in (4, 8):
+        b = tgf.tgf_workspace_bytes_sun(nc, 1, tgf.make_geoms([(4, 4, 16, 16)]), F64)
+        # two link buffers + X, each 4 nc^2 complex128 per site (shared regions cancel)
+        assert b - b2 == pytest.approx(V * 3 * 4 * (nc * nc - 4) * 16, abs=4096)
+    assert tgf.tgf_workspace_bytes_sun(4, 1, g, F64) > 0          # twist 3 < 4
+    assert tgf.tgf_workspace_bytes_sun(3, 1, g, F64) == 0         # twist 3 >= 3
+    assert tgf.tgf_workspace_bytes_sun(1, 1, g, F64) == 0
+    assert tgf.tgf_workspace_bytes_sun(9, 1, g, F64) == 0
+    assert tgf.tgf_workspace_bytes_sun(4, 1, g, tgf.TGF_F32_C12) == 0
+    # sites per configuration capped at 2^28 / nc^2 - 256
+    big = tgf.make_geoms([(64, 64, 64, 64)])
+    assert tgf.tgf_workspace_bytes_sun(2, 1, big, F64) > 0
+    assert tgf.tgf_workspace_bytes_sun(8, 1, big, F64) == 0
+    ctx = ctypes.c_void_p()
+    assert tgf.tgf_create_sun(ctypes.byref(ctx), 9, 1, g, F64, ctypes.c_void_p(FAKE), 1 << 40,
+                              None) == tgf.TGF_E_INVAL
+    assert tgf.tgf_create_sun(ctypes.byref(ctx), 4, 1, g, tgf.TGF_F32_FULL,
+                              ctypes.c_void_p(FAKE), 1 << 40, None) == tgf.TGF_E_UNSUPPORTED
+    assert tgf.tgf_create_sun(ctypes.byref(ctx), 4, 1, g, F64, ctypes.c_void_p(FAKE), 1024,
+                              None) == tgf.TGF_E_SIZE
+    assert not ctx.value
