@@ -244,7 +244,7 @@ MC_BYTES_PER_LINK = (4 + 0.5) * 144 / 0.5
 MC_FLOPS_PER_LINK = 2484 + 198 + 3 * 240
 MC_B = 0.5
 MC_N_OR = 3
-MC_CPU_CFGS = 16
+MC_CPU_CFGS = 64
 
 
 def time_mc(tgf, torch, cfgs, inputs, reps, cpu=True):
@@ -315,6 +315,95 @@ def time_mc(tgf, torch, cfgs, inputs, reps, cpu=True):
     return out
 
 
+# General SU(N) (FP64, row-per-lane kernels), per site per RK3 step.
+# Bytes: links read + written every stage, 3 x 2 x 4 x N^2 x 16, and the full
+# N x N accumulator X written, read + written, read: 4 x 4 x N^2 x 16.
+# Flops: per link and stage 25 N x N products (6 staples of 2, U S, 11 Horner
+# steps of the exponential, exp(X) U) of 8 N^3 flop, plus the staple sums
+# (6 N^2 complex multiply-adds), P_ah and the RK update (~2 N^2 of them).
+def sun_bytes_per_site_step(N):
+    return 3 * 2 * 4 * N * N * 16 + 4 * 4 * N * N * 16
+
+
+def sun_flops_per_site_step(N):
+    return 4 * 3 * (25 * 8 * N ** 3 + 8 * 8 * N * N)
+
+
+def sun_mode(tgf, torch, args):
+    """SU(N) flow of a batch of l^2 x (N l)^2 boxes (the TGF geometry), l =
+    args.sun_l, twist k = 1, near-identity links, about args.sun_sites sites in
+    total, flowed for args.sun_steps steps of eps; site-updates/s, the stage
+    kernel's HIP-event average and its ALU roofline."""
+    from paper_2107_03747_amd import gen
+    N, l = args.nc, args.sun_l
+    d = (l, l, N * l, N * l)
+    V = math.prod(d)
+    n_cfg = max(1, args.sun_sites // V)
+    log(f"SU({N}): {n_cfg} x {'x'.join(map(str, d))}")
+    links = [gen.near_identity_n(d, N, 0.3, seed=6000 + k, device="cuda") for k in range(n_cfg)]
+    t_end = args.sun_steps * EPS
+    f = tgf.Flow([d] * n_cfg, "f64", nc=N)
+    f.load_all(links)
+    f.flow(EPS, t_end, 0.0)                      # warm-up (graph capture)
+    times = []
+    for _ in range(max(1, args.steps // 5)):
+        f.load_all(links)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rows = f.flow(EPS, t_end, 0.0)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    dt = min(times)
+    site_updates = n_cfg * V * args.sun_steps
+    f.load_all(links)
+    f.flow(EPS, t_end, 0.0, 0, tgf.TGF_TIMING)
+    tm = f.timing()
+    stage_ms = tm["stage_ms"] / tm["stage_launches"]
+    site_stages = 3 * tm["stage_site_updates"] / tm["stage_launches"]
+    tflops = site_stages * sun_flops_per_site_step(N) / 3 / (stage_ms * 1e-3) / 1e12
+    gbs = site_stages * sun_bytes_per_site_step(N) / 3 / (stage_ms * 1e-3) / 1e9
+    out = {
+        "metric": f"SU({N}) flowed site-updates/s (FP64)",
+        "value": round(site_updates / dt, 1),
+        "unit": "site-updates/s",
+        "nc": N,
+        "ms_per_flow": round(dt * 1e3, 3),
+        "config": {"workload": f"{n_cfg} x {'x'.join(map(str, d))}, twist k=1, near-identity "
+                               f"links eps 0.3, {args.sun_steps} steps of {EPS}",
+                   "n_configs": n_cfg, "sites": n_cfg * V},
+        "t2E_last_cfg0": float(rows[-1, 0, 2]),
+        "roofline": {"kernel": f"sun_stage_kernel<{N}>", "bound": "alu",
+                     "achieved": round(tflops, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
+                     "unit": "TFLOP/s", "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
+                     "hbm_gbs_algorithmic": round(gbs, 1),
+                     "avg_launch_ms": round(stage_ms, 4),
+                     "flops_per_site_step": sun_flops_per_site_step(N),
+                     "bytes_per_site_step": sun_bytes_per_site_step(N)},
+    }
+    if not args.no_cpu:
+        import numpy as np
+        import oracle
+        oracle.build(force=False)
+        oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+        U = links[0].cpu().numpy().copy()
+        k = max(1, min(args.sun_steps, 3))
+        t0 = time.perf_counter()
+        ref = oracle.sun_flow(U, d, EPS, k * EPS, 0.0)
+        tc = time.perf_counter() - t0
+        g = tgf.Flow([d], "f64", nc=N)
+        g.load(0, links[0])
+        rg = g.flow(EPS, k * EPS, 0.0)
+        out["cpu_baseline"] = {"value": round(V * k / tc, 1), "unit": "site-updates/s",
+                               "cores": oracle.get_threads(), "host_cpu": host_cpu(),
+                               "kind": "oracle",
+                               "sample": f"configuration 0, {k} steps: {V * k} site-updates "
+                                         f"in {tc:.2f} s"}
+        out["t2E_gpu_oracle_sample"] = [float(rg[-1, 0, 2]), float(ref[-1, 2])]
+        out["t2E_rel_err_vs_oracle_sample"] = float(abs(rg[-1, 0, 2] - ref[-1, 2]) /
+                                                    abs(ref[-1, 2]))
+    print(json.dumps(out), flush=True)
+
+
 def copy_mode(tgf, torch, args):
     """Plain copy of a known size with the library's copy kernel: reads and
     writes `bytes` each per launch.  Used to calibrate the HBM counters."""
@@ -348,9 +437,14 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mc", action="store_true")
     ap.add_argument("--mc-reps", type=int, default=3)
-    ap.add_argument("--mode", choices=("flow", "copy", "mc"), default="flow",
+    ap.add_argument("--mode", choices=("flow", "copy", "mc", "sun"), default="flow",
                     help="copy: time the library's plain HBM copy kernel (counter calibration); "
-                         "mc: time only the Monte Carlo on the batch geometry")
+                         "mc: time only the Monte Carlo on the batch geometry; "
+                         "sun: time the general SU(N) flow (--nc)")
+    ap.add_argument("--nc", type=int, default=4)
+    ap.add_argument("--sun-l", type=int, default=4)
+    ap.add_argument("--sun-sites", type=int, default=1 << 20)
+    ap.add_argument("--sun-steps", type=int, default=20)
     ap.add_argument("--copy-gib", type=float, default=2.0)
     args = ap.parse_args()
 
@@ -366,6 +460,9 @@ def main():
 
     if args.mode == "copy":
         copy_mode(tgf, torch, args)
+        return
+    if args.mode == "sun":
+        sun_mode(tgf, torch, args)
         return
 
     cfgs = batch_workload() if args.workload == "batch" else large_workload()

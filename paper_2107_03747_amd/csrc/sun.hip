@@ -190,9 +190,7 @@ __device__ __forceinline__ RowN<N> omega_row(gptr<const v2<double>> W, const Cfg
                                              const Geo &g, const Grp &gr, RowN<N> &U) {
     const int st = c.stride, r = gr.r;
     RowN<N> S = row_zero<N>();
-#pragma unroll
-    for (int nu = 0; nu < 4; nu++) {
-        if (nu == MU) continue;
+    auto add_staples = [&](int nu) {
         const int k = tw_exp<N>(c, MU, nu);
         // upper: U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
         RowN<N> t = mm_nd(load_row<N>(W, st, nu, r, g.i + g.up(MU)),
@@ -208,6 +206,18 @@ __device__ __forceinline__ RowN<N> omega_row(gptr<const v2<double>> W, const Cfg
         z = {1.0, 0.0};
         if (k && g.n(MU) == 0 && g.back(nu) == 0) z = zphase<N>(k);
         row_axpy(S, z, t);
+    };
+    if constexpr (N == 3) {
+#pragma unroll
+        for (int nu = 0; nu < 4; nu++)
+            if (nu != MU) add_staples(nu);
+    } else {
+        // one direction at a time: unrolled, the loads of all six staples are
+        // live together and the kernel spills from N = 5 on (and N = 2 keeps
+        // two waves per SIMD this way)
+#pragma unroll 1
+        for (int nu = 0; nu < 4; nu++)
+            if (nu != MU) add_staples(nu);
     }
     U = load_row<N>(W, st, MU, r, g.i);
     return mm_nn(U, S, gr);
@@ -395,26 +405,19 @@ __device__ __forceinline__ double herm_dot(const RowN<N> &a, const RowN<N> &b) {
 template <int N>
 __device__ __forceinline__ void measure_site_n(gptr<const v2<double>> W, const CfgDesc &c,
                                                const Geo &g, const Grp &gr, double v[4]) {
-    double rp[6] = {0, 0, 0, 0, 0, 0};
-    const RowN<N> G01 = clover_row<N>(W, c, g, gr, 0, 1, rp[0]);
-    const RowN<N> G23 = clover_row<N>(W, c, g, gr, 2, 3, rp[5]);
-    double e = herm_dot(G01, G01) + herm_dot(G23, G23);
-    double q = herm_dot(G01, G23);
-    {
-        const RowN<N> G02 = clover_row<N>(W, c, g, gr, 0, 2, rp[1]);
-        const RowN<N> G13 = clover_row<N>(W, c, g, gr, 1, 3, rp[4]);
-        e += herm_dot(G02, G02) + herm_dot(G13, G13);
-        q -= herm_dot(G02, G13);
+    // the three dual plane pairs (01,23), (02,13), (03,12), one at a time
+    double e = 0.0, q = 0.0, p = 0.0;
+#pragma unroll 1
+    for (int pr = 0; pr < 3; pr++) {
+        const int a1 = pr + 1;                         // planes (0, a1) and (b0, b1)
+        const int b0 = pr == 2 ? 1 : (pr == 1 ? 1 : 2);
+        const int b1 = pr == 0 ? 3 : (pr == 1 ? 3 : 2);
+        const RowN<N> Ga = clover_row<N>(W, c, g, gr, 0, a1, p);
+        const RowN<N> Gb = clover_row<N>(W, c, g, gr, b0, b1, p);
+        e += herm_dot(Ga, Ga) + herm_dot(Gb, Gb);
+        const double d = herm_dot(Ga, Gb);
+        q += pr == 1 ? -d : d;
     }
-    {
-        const RowN<N> G03 = clover_row<N>(W, c, g, gr, 0, 3, rp[2]);
-        const RowN<N> G12 = clover_row<N>(W, c, g, gr, 1, 2, rp[3]);
-        e += herm_dot(G03, G03) + herm_dot(G12, G12);
-        q += herm_dot(G03, G12);
-    }
-    double p = 0.0;
-#pragma unroll
-    for (int k = 0; k < 6; k++) p += rp[k];
     v[0] += e;
     v[1] += q * 0.025330295910584444;   // 1 / (4 pi^2)
     v[2] += p;
