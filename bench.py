@@ -94,6 +94,11 @@ def flops_per_site_stage(storage, variant, part=1):
     """Real FP operations per site for one RK stage, by kernel."""
     c12 = storage == "f32c12"
     upd = R2 if c12 else MM
+    if variant.startswith("site_alg"):
+        # six two-row plaquettes projected to su(3) (r2_proj_ah ~35, +-accumulate 16),
+        # twelve lower staples (2 products each), four U S products + projection
+        return (18 * R2 + 6 * (35 + 16) + 28 * MM + 4 * 16 + 4 * (EXP + upd + XUPD)
+                + (REBUILD * 44 if c12 else 0))
     if variant.startswith("site"):
         return 46 * MM + 4 * (EXP + upd + XUPD) + (REBUILD * 44 if c12 else 0)
     if variant.startswith("link"):
@@ -499,8 +504,13 @@ def main():
     alu_frac = tflops / ALU_PEAK_TFLOPS
     alu = alu_frac >= hbm_frac
     traffic, traffic_src = profiled_traffic(variant, args.storage, args.workload)
-    kname = {"site": "stage_site_kernel", "link": "stage_link_kernel",
-             "split": "split_link_kernel"}[variant.split("_")[0]]
+    if variant.startswith("site_alg3"):
+        kname = "stage_site_alg3_kernel"
+    elif variant.startswith("site_alg"):
+        kname = "stage_site_alg_kernel"
+    else:
+        kname = {"site": "stage_site_kernel", "link": "stage_link_kernel",
+                 "split": "split_link_kernel"}[variant.split("_")[0]]
     targ = "double, 9" if args.storage == "f64" else ("float, 6" if args.storage == "f32c12"
                                                       else "float, 9")
     roofline = {

@@ -29,13 +29,12 @@
 
 namespace tgf {
 
-// RK stage tail for one link: X = B eps F + A X_old; W_out = exp(X) W_in.
+// RK stage tail for one link, from Z = B eps F in the 8-real form:
+// X = Z + A X_old; W_out = exp(X) W_in.
 template <class R, int NE>
-__device__ __forceinline__ void update_link(const Links<R, NE> &W, gptr<v2<R>> Wout,
-                                            gptr<v2<R>> X, int stride, int mu, int i,
-                                            const M3<R> &Omega, R beps, R a, int stage,
-                                            int reunit) {
-    Alg<R> Z = proj_ah(Omega, -beps);
+__device__ __forceinline__ void update_link_z(const Links<R, NE> &W, gptr<v2<R>> Wout,
+                                              gptr<v2<R>> X, int stride, int mu, int i,
+                                              Alg<R> Z, R a, int stage, int reunit) {
     gptr<v2<R>> xp = X + (size_t)(mu * 4) * stride;
     const unsigned u = lane_off<R>(i);
     if (stage > 0) {
@@ -68,6 +67,15 @@ __device__ __forceinline__ void update_link(const Links<R, NE> &W, gptr<v2<R>> W
     }
     if (reunit) reunitarise(N);
     store_link<R, NE>(Wout, stride, mu, i, N);
+}
+
+// RK stage tail from Omega: B eps F = -B eps P_ah(Omega).
+template <class R, int NE>
+__device__ __forceinline__ void update_link(const Links<R, NE> &W, gptr<v2<R>> Wout,
+                                            gptr<v2<R>> X, int stride, int mu, int i,
+                                            const M3<R> &Omega, R beps, R a, int stage,
+                                            int reunit) {
+    update_link_z<R, NE>(W, Wout, X, stride, mu, i, proj_ah(Omega, -beps), a, stage, reunit);
 }
 
 __constant__ double kRkA[3] = {0.0, -17.0 / 9.0, -1.0};
@@ -141,6 +149,102 @@ __global__ __launch_bounds__(256) void stage_site_kernel(StageArgs a) {
     site_lower_update<R, NE, 1>(W, Wout, X, c, g, acc[1], beps, ac, a);
     site_lower_update<R, NE, 2>(W, Wout, X, c, g, acc[2], beps, ac, a);
     site_lower_update<R, NE, 3>(W, Wout, X, c, g, acc[3], beps, ac, a);
+}
+
+// Site variant with su(3) force accumulators.  P_ah is linear and
+// P_ah(P^+) = -P_ah(P), so each upper plaquette Z^* P_{mu nu}(n) enters its two
+// links as +-P_ah in the 8-real form, taken from its two computed rows
+// (r2_proj_ah, no third row); only the lower staples are summed as 3x3
+// matrices and multiplied by U_mu(n).  The four force accumulators take
+// 4 x 8 reals instead of 4 x 18.
+template <class R, int NE, int MU>
+__device__ __forceinline__ void site_alg_update(const Links<R, NE> &W, gptr<v2<R>> Wout,
+                                                gptr<v2<R>> X, const CfgDesc &c, const Geo &g,
+                                                const Alg<R> &f, R beps, R ac,
+                                                const StageArgs &a) {
+    M3<R> S;
+    m_zero(S);
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == MU) continue;
+        acc_lower_staple(S, W, c, g, MU, nu);
+    }
+    const Alg<R> lo = proj_ah(mul_nn(W(MU, g.i), S), R(1));
+    Alg<R> Z;
+#pragma unroll
+    for (int k = 0; k < 8; k++) Z.a[k] = -beps * (f.a[k] + lo.a[k]);
+    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, a.reunit);
+}
+
+template <class R, int NE>
+__device__ __forceinline__ void site_alg_body(const StageArgs &a) {
+    const int nb = (a.n_tiles + 3) >> 2;
+    const int b = remap_block(blockIdx.x, nb, a.xcd);
+    if (b >= nb) return;
+    const int tile = b * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= a.n_tiles) return;
+    const int ci = find_cfg(a.tile_start, a.n_act, tile);
+    const CfgDesc c = a.cfgs[ci];
+    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
+    if (i >= c.V) return;
+
+    const int in = (c.cur + 3 * a.step + a.stage) & 1;
+    const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
+    gptr<v2<R>> Wout = as_global<R>(in ? c.W[0] : c.W[1]);
+    gptr<v2<R>> X = as_global<R>(c.X);
+    const double eps = a.step < c.n_full ? a.eps : c.eps_last;
+    const R beps = (R)(kRkB[a.stage] * eps);
+    const R ac = (R)kRkA[a.stage];
+    const Geo g = make_geo(c, i);
+
+    Alg<R> f[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++)
+#pragma unroll
+        for (int k = 0; k < 8; k++) f[mu].a[k] = R(0);
+#pragma unroll
+    for (int mu = 0, p = 0; mu < 4; mu++)
+#pragma unroll
+        for (int nu = mu + 1; nu < 4; nu++, p++) {
+            // rows 0,1 of U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+, times Z^*; a
+            // cube root of unity keeps the third row conj(row0 x row1)
+            R2<R> P = r2_of(W(mu, i));
+            P = r2_mul_nn(P, W(nu, i + g.up(mu)));
+            P = r2_mul_nd(P, W(mu, i + g.up(nu)));
+            P = r2_mul_nd(P, W(nu, i));
+            const int k = c.tw[p];
+            if (k && g.n(mu) == 0 && g.n(nu) == 0) r2_scale(P, cconj(omega_pow<R>(k)));
+            R A8[8];
+            r2_proj_ah(P, R(1), A8);
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                f[mu].a[t] += A8[t];
+                f[nu].a[t] -= A8[t];
+            }
+        }
+    site_alg_update<R, NE, 0>(W, Wout, X, c, g, f[0], beps, ac, a);
+    site_alg_update<R, NE, 1>(W, Wout, X, c, g, f[1], beps, ac, a);
+    site_alg_update<R, NE, 2>(W, Wout, X, c, g, f[2], beps, ac, a);
+    site_alg_update<R, NE, 3>(W, Wout, X, c, g, f[3], beps, ac, a);
+}
+
+// Register budgets: FP64 keeps the whole working set in 512 registers (one
+// wave per SIMD); FP32 is capped at 256 (two waves per SIMD).
+template <class R, int NE>
+__global__ __launch_bounds__(256) void stage_site_alg_kernel(StageArgs a) {
+    site_alg_body<R, NE>(a);
+}
+
+template <class R, int NE>
+__global__ __launch_bounds__(256, 2) void stage_site_alg2_kernel(StageArgs a) {
+    site_alg_body<R, NE>(a);
+}
+
+// the same with at most 168 registers, so three waves share a SIMD (the
+// compiler spills the excess to scratch)
+template <class R, int NE>
+__global__ __launch_bounds__(256, 3) void stage_site_alg3_kernel(StageArgs a) {
+    site_alg_body<R, NE>(a);
 }
 
 // One thread per link: a work-group is one tile of 64 sites x 4 directions,
@@ -722,13 +826,18 @@ const char *variant_name(int v) {
         case V_LINK_XCD: return "link_xcd";
         case V_SPLIT: return "split";
         case V_SPLIT_XCD: return "split_xcd";
+        case V_SITE_ALG: return "site_alg";
+        case V_SITE_ALG_XCD: return "site_alg_xcd";
+        case V_SITE_ALG3: return "site_alg3";
+        case V_SITE_ALG3_XCD: return "site_alg3_xcd";
         default: return "?";
     }
 }
 
 template <class R, int NE>
 static hipError_t launch_stage_t(int variant, int part, hipStream_t s, const StageArgs &a) {
-    const bool xcd = variant == V_SITE_XCD || variant == V_LINK_XCD || variant == V_SPLIT_XCD;
+    const bool xcd = variant == V_SITE_XCD || variant == V_LINK_XCD || variant == V_SPLIT_XCD ||
+                     variant == V_SITE_ALG_XCD || variant == V_SITE_ALG3_XCD;
     StageArgs b = a;
     b.xcd = xcd ? 1 : 0;
     const int site_blocks = xcd ? ((a.n_tiles + 3) / 4 + 7) / 8 * 8 : (a.n_tiles + 3) / 4;
@@ -742,6 +851,14 @@ static hipError_t launch_stage_t(int variant, int part, hipStream_t s, const Sta
         return hipSuccess;   // single-kernel variants have no part 0
     } else if (variant == V_SITE || variant == V_SITE_XCD) {
         hipLaunchKernelGGL((stage_site_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
+    } else if (variant == V_SITE_ALG || variant == V_SITE_ALG_XCD) {
+        if constexpr (sizeof(R) == 8)
+            hipLaunchKernelGGL((stage_site_alg_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
+        else
+            hipLaunchKernelGGL((stage_site_alg2_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s,
+                               b);
+    } else if (variant == V_SITE_ALG3 || variant == V_SITE_ALG3_XCD) {
+        hipLaunchKernelGGL((stage_site_alg3_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
     } else {
         hipLaunchKernelGGL((stage_link_kernel<R, NE>), dim3(tile_blocks), dim3(256), 0, s, b);
     }

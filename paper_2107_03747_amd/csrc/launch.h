@@ -20,7 +20,12 @@ enum Variant {
     V_SPLIT = 4,      // two kernels per stage: plaquette algebra A_{mu nu}(n), then
                       // force from A and its conjugated neighbours + update
     V_SPLIT_XCD = 5,  // V_SPLIT with XCD-contiguous tile order
-    V_COUNT = 6
+    V_SITE_ALG = 6,   // V_SITE with su(3) (8-real) force accumulators, upper
+                      // plaquettes projected from their two computed rows
+    V_SITE_ALG_XCD = 7,
+    V_SITE_ALG3 = 8,  // V_SITE_ALG capped at 168 registers (three waves per SIMD)
+    V_SITE_ALG3_XCD = 9,
+    V_COUNT = 10
 };
 inline bool variant_is_split(int v) { return v == V_SPLIT || v == V_SPLIT_XCD; }
 const char *variant_name(int v);
