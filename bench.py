@@ -349,6 +349,10 @@ def sun_mode(tgf, torch, args):
     t_end = args.sun_steps * EPS
     f = tgf.Flow([d] * n_cfg, "f64", nc=N)
     f.load_all(links)
+    v = f.autotune(None) if args.variant is None else args.variant
+    f.set_variant(v)
+    rows_per_lane = int(tgf.tgf_sun_rows_per_lane(N, v))
+    log(f"SU({N}): variant {v} ({rows_per_lane} rows per lane)")
     f.flow(EPS, t_end, 0.0)                      # warm-up (graph capture)
     times = []
     for _ in range(max(1, args.steps // 5)):
@@ -377,7 +381,8 @@ def sun_mode(tgf, torch, args):
                                f"links eps 0.3, {args.sun_steps} steps of {EPS}",
                    "n_configs": n_cfg, "sites": n_cfg * V},
         "t2E_last_cfg0": float(rows[-1, 0, 2]),
-        "roofline": {"kernel": f"sun_stage_kernel<{N}>", "bound": "alu",
+        "rows_per_lane": rows_per_lane,
+        "roofline": {"kernel": f"sun_stage_kernel<{N}, {rows_per_lane}>", "bound": "alu",
                      "achieved": round(tflops, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
                      "unit": "TFLOP/s", "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
                      "hbm_gbs_algorithmic": round(gbs, 1),
@@ -396,6 +401,7 @@ def sun_mode(tgf, torch, args):
         ref = oracle.sun_flow(U, d, EPS, k * EPS, 0.0)
         tc = time.perf_counter() - t0
         g = tgf.Flow([d], "f64", nc=N)
+        g.set_variant(v)
         g.load(0, links[0])
         rg = g.flow(EPS, k * EPS, 0.0)
         out["cpu_baseline"] = {"value": round(V * k / tc, 1), "unit": "site-updates/s",

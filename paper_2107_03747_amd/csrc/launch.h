@@ -78,11 +78,15 @@ hipError_t launch_check_final(hipStream_t s, const double *partials, int ntiles,
 
 // General SU(N), FP64 full storage [mu][N^2][stride], 2 <= nc <= 8 (sun.hip).
 // Same tile table, ping-pong and partials conventions as the SU(3) launchers.
-hipError_t launch_stage_sun(int nc, hipStream_t s, const CfgDesc *cfgs, const int *tile_start,
-                            int n_act, int n_tiles, int step, int stage, double eps);
-hipError_t launch_measure_sun(int nc, hipStream_t s, const CfgDesc *cfgs, const int *tile_start,
-                              int n_cfg, int n_tiles, const MeasSlot *slots, double *partials,
-                              int buf_sel);
+// variant selects the rows held per lane (sun_rows_per_lane); -1 = 0.
+int sun_variant_count(int nc);
+int sun_rows_per_lane(int nc, int variant);   // 0 if the variant does not exist
+hipError_t launch_stage_sun(int nc, int variant, hipStream_t s, const CfgDesc *cfgs,
+                            const int *tile_start, int n_act, int n_tiles, int step, int stage,
+                            double eps);
+hipError_t launch_measure_sun(int nc, int variant, hipStream_t s, const CfgDesc *cfgs,
+                              const int *tile_start, int n_cfg, int n_tiles, const MeasSlot *slots,
+                              double *partials, int buf_sel);
 hipError_t launch_pack_sun(int nc, hipStream_t s, const void *src, void *W, int V, int stride);
 hipError_t launch_unpack_sun(int nc, hipStream_t s, const void *W, void *dst, int V, int stride);
 hipError_t launch_check_sun(int nc, bool canon, hipStream_t s, const void *src, int V, int stride,

@@ -182,7 +182,9 @@ struct tgf_ctx {
     bool c12() const { return st == TGF_F32_C12; }
     int ne() const { return general ? nc * nc : (st == TGF_F32_C12 ? 6 : 9); }
     int x_entries() const { return general ? nc * nc : 4; }
+    int variant_count() const { return general ? sun_variant_count(nc) : V_COUNT; }
     int effective_variant() const {
+        if (general) return variant >= 0 ? variant : 0;
         if (variant >= 0) return variant;
         return st == TGF_F64_FULL ? V_LINK : V_SITE;
     }
@@ -260,14 +262,15 @@ tgf_status run_launches(tgf_ctx *c, const std::vector<Launch> &ls, double eps, b
             case 0:
             case 4:
                 if (c->general)
-                    return launch_stage_sun(c->nc, s, c->d_desc(), c->d_tiles(), l.n_act, l.grid,
-                                            l.step, l.stage, eps);
+                    return launch_stage_sun(c->nc, variant, s, c->d_desc(), c->d_tiles(), l.n_act,
+                                            l.grid, l.step, l.stage, eps);
                 return launch_stage(variant, l.kind == 0 ? 1 : 0, c->prec(), c->c12(), s,
                                     c->d_desc(), c->d_tiles(), l.n_act, l.grid, l.step, l.stage,
                                     eps, l.reunit);
             case 1:
                 if (c->general)
-                    return launch_measure_sun(c->nc, s, c->d_desc(), c->d_tiles(), l.n_act, l.grid,
+                    return launch_measure_sun(c->nc, variant, s, c->d_desc(), c->d_tiles(),
+                                              l.n_act, l.grid,
                                               c->d_meas() + (size_t)l.event * c->n_cfg,
                                               c->d_partials(), l.step);
                 return launch_measure(c->prec(), c->c12(), s, c->d_desc(), c->d_tiles(), l.n_act,
@@ -605,8 +608,9 @@ tgf_status tgf_measure(tgf_ctx *c, tgf_obs *out_host) {
                            c->stream));
     HIP_TRY(launch_fill_int(c->stream, c->d_flag(), 1, 0));
     if (c->general)
-        HIP_TRY(launch_measure_sun(c->nc, c->stream, c->d_desc(), c->d_tiles(), c->n_cfg,
-                                   ts[c->n_cfg], c->d_meas(), c->d_partials(), -1));
+        HIP_TRY(launch_measure_sun(c->nc, c->effective_variant(), c->stream, c->d_desc(),
+                                   c->d_tiles(), c->n_cfg, ts[c->n_cfg], c->d_meas(),
+                                   c->d_partials(), -1));
     else
         HIP_TRY(launch_measure(c->prec(), c->c12(), c->stream, c->d_desc(), c->d_tiles(),
                                c->n_cfg, ts[c->n_cfg], c->d_meas(), c->d_partials(), -1));
@@ -885,6 +889,12 @@ tgf_status tgf_get_timing(tgf_ctx *c, tgf_timing *out) {
 
 int32_t tgf_variant_count(void) { return V_COUNT; }
 
+int32_t tgf_sun_variant_count(int32_t nc) { return sun_variant_count(nc); }
+
+int32_t tgf_sun_rows_per_lane(int32_t nc, int32_t variant) {
+    return sun_rows_per_lane(nc, variant);
+}
+
 const char *tgf_variant_name(int32_t v) {
     if (v < 0 || v >= V_COUNT) return "default";
     return variant_name(v);
@@ -894,9 +904,7 @@ tgf_status tgf_set_variant(tgf_ctx *c, int32_t v) {
     g_err.clear();
     tgf_status s = check_ctx(c);
     if (s) return s;
-    if (v < -1 || v >= V_COUNT) return fail(TGF_E_INVAL, "variant out of range");
-    if (c->general && v != -1)
-        return fail(TGF_E_UNSUPPORTED, "SU(N) contexts have a single stage kernel");
+    if (v < -1 || v >= c->variant_count()) return fail(TGF_E_INVAL, "variant out of range");
     c->variant = v;
     return TGF_OK;
 }
@@ -912,6 +920,7 @@ static std::string tune_key(tgf_ctx *c) {
     else
         k << "unknown";
     k << "/st" << (int)c->st;
+    if (c->general) k << "/nc" << c->nc;
     for (auto &h : c->L.cfg) k << "/" << h.d[0] << "x" << h.d[1] << "x" << h.d[2] << "x" << h.d[3];
     std::string s = k.str();
     for (char &ch : s)
@@ -926,14 +935,13 @@ tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path) {
     for (int k = 0; k < c->n_cfg; k++)
         if (!c->L.cfg[k].loaded)
             return fail(TGF_E_STATE, "config " + std::to_string(k) + " not loaded");
-    if (c->general) return TGF_OK;   // one stage kernel: nothing to choose
     const std::string key = tune_key(c);
     if (cache_path) {
         std::ifstream in(cache_path);
         std::string k2;
         int v;
         while (in >> k2 >> v)
-            if (k2 == key && v >= 0 && v < V_COUNT) {
+            if (k2 == key && v >= 0 && v < c->variant_count()) {
                 c->variant = v;
                 return TGF_OK;
             }
@@ -958,13 +966,16 @@ tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path) {
     float best_ms = 1e30f;
     const int reps = 5;
     auto stage0 = [&](int v) {
+        if (c->general)
+            return launch_stage_sun(c->nc, v, c->stream, c->d_desc(), c->d_tiles(), n, ts[n], 0,
+                                    0, 0.01);
         hipError_t err = hipSuccess;
         for (int part = 0; part < 2 && err == hipSuccess; part++)
             err = launch_stage(v, part, c->prec(), c->c12(), c->stream, c->d_desc(),
                                c->d_tiles(), n, ts[n], 0, 0, 0.01, 0);
         return err;
     };
-    for (int v = 0; v < V_COUNT; v++) {
+    for (int v = 0; v < c->variant_count(); v++) {
         hipError_t err = stage0(v);
         if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
         for (int r = 0; r < reps && err == hipSuccess; r++) err = stage0(v);

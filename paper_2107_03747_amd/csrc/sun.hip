@@ -9,13 +9,15 @@
 // with Luscher's RK3 scheme in the same low-storage form as the SU(3) path,
 // X_i = B_i eps F + A_i X_{i-1}, W_{i+1} = exp(X_i) W_i.
 //
-// Work decomposition ("row per lane"): the N x N matrix of a link is spread
-// over N consecutive lanes of a wavefront, lane r holding row r, so a wave
-// holds G = floor(64 / N) links.  In a product C = A B every lane forms its
-// own row of C: its row of A is local, the rows of B come from the other
-// lanes of its group through cross-lane permutes (ds_bpermute).  A^+ enters
-// through the column of A that a lane needs (gathered the same way).  No
-// matrix ever sits whole in one lane, so N = 8 needs 32 registers per row.
+// Work decomposition ("R rows per lane"): the N x N matrix of a link is spread
+// over L = N / R consecutive lanes of a wavefront, lane l holding rows
+// l R .. l R + R - 1, so a wave holds G = floor(64 / L) links.  In a product
+// C = A B every lane forms its own rows of C: its rows of A are local, the
+// rows of B held by the other lanes of its group come through cross-lane
+// permutes (ds_bpermute), each fetched entry then serving R multiply-adds.
+// A^+ enters through the columns of A that a lane needs (gathered the same
+// way).  R = N is one thread per link with no permutes; R = 1 keeps the
+// fewest registers.  The choice is per context (the SU(N) variants).
 //
 // Storage: FP64, [mu][entry][site] with entry = r N + j, the structure of
 // arrays of the SU(3) full storage; the RK accumulator X is a full N x N
@@ -31,138 +33,191 @@
 
 namespace tgf {
 
-template <int N>
-struct RowN {
-    cx<double> e[N];
+// rows l R .. l R + R - 1 of an N x N matrix
+template <int N, int R>
+struct Blk {
+    cx<double> e[R][N];
 };
 
-// this lane's place in its group of N lanes
+// this lane's place in its group of L = N / R lanes
 struct Grp {
     int base;   // first lane of the group
-    int r;      // row held by this lane
+    int l;      // index of this lane in the group
 };
 
-template <int N>
-__device__ __forceinline__ RowN<N> row_zero() {
-    RowN<N> o;
+// global row index of local row i
+template <int N, int R>
+__device__ __forceinline__ int row_index(const Grp &g, int i) {
+    return (N == R) ? i : g.l * R + i;
+}
+
+template <int N, int R>
+__device__ __forceinline__ Blk<N, R> blk_zero() {
+    Blk<N, R> o;
 #pragma unroll
-    for (int j = 0; j < N; j++) o.e[j] = {0.0, 0.0};
+    for (int i = 0; i < R; i++)
+#pragma unroll
+        for (int j = 0; j < N; j++) o.e[i][j] = {0.0, 0.0};
     return o;
 }
 
-// the row held by lane src of the wave
-template <int N>
-__device__ __forceinline__ RowN<N> row_from(const RowN<N> &m, int src) {
-    RowN<N> o;
+// the rows held by lane base + q of the group (the block itself when L = 1)
+template <int N, int R>
+__device__ __forceinline__ Blk<N, R> blk_from(const Blk<N, R> &m, const Grp &g, int q) {
+    if constexpr (N == R) {
+        return m;
+    } else {
+        Blk<N, R> o;
+        const int src = g.base + q;
 #pragma unroll
-    for (int j = 0; j < N; j++) {
-        o.e[j].x = __shfl(m.e[j].x, src);
-        o.e[j].y = __shfl(m.e[j].y, src);
+        for (int i = 0; i < R; i++)
+#pragma unroll
+            for (int j = 0; j < N; j++) {
+                o.e[i][j].x = __shfl(m.e[i][j].x, src);
+                o.e[i][j].y = __shfl(m.e[i][j].y, src);
+            }
+        return o;
     }
-    return o;
 }
 
 // entry r of a row for a lane-dependent r, by selection (no register indexing)
 template <int N>
-__device__ __forceinline__ cx<double> pick(const RowN<N> &m, int r) {
-    cx<double> v = m.e[0];
+__device__ __forceinline__ cx<double> pick(const cx<double> (&row)[N], int r) {
+    cx<double> v = row[0];
 #pragma unroll
     for (int j = 1; j < N; j++)
-        if (r == j) v = m.e[j];
+        if (r == j) v = row[j];
     return v;
 }
 
-template <int N>
+template <int N, int R>
 __device__ __forceinline__ double group_sum(double v, const Grp &g) {
-    double s = 0.0;
+    if constexpr (N == R) {
+        return v;
+    } else {
+        double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < N; k++) s += __shfl(v, g.base + k);
-    return s;
+        for (int q = 0; q < N / R; q++) s += __shfl(v, g.base + q);
+        return s;
+    }
 }
 
-// row r of A B
-template <int N>
-__device__ __forceinline__ RowN<N> mm_nn(const RowN<N> &a, const RowN<N> &b, const Grp &g) {
-    RowN<N> c = row_zero<N>();
+// own rows of A B
+template <int N, int R>
+__device__ __forceinline__ Blk<N, R> mm_nn(const Blk<N, R> &a, const Blk<N, R> &b, const Grp &g) {
+    Blk<N, R> c = blk_zero<N, R>();
 #pragma unroll
-    for (int k = 0; k < N; k++) {
-        const RowN<N> bk = row_from(b, g.base + k);
+    for (int q = 0; q < N / R; q++) {
+        const Blk<N, R> bq = blk_from<N, R>(b, g, q);
 #pragma unroll
-        for (int j = 0; j < N; j++) c.e[j] = cmadd(c.e[j], a.e[k], bk.e[j]);
+        for (int kk = 0; kk < R; kk++)
+#pragma unroll
+            for (int i = 0; i < R; i++)
+#pragma unroll
+                for (int j = 0; j < N; j++)
+                    c.e[i][j] = cmadd(c.e[i][j], a.e[i][q * R + kk], bq.e[kk][j]);
     }
     return c;
 }
 
-// row r of A B^+: (A B^+)_{rj} = sum_k A_{rk} conj(B_{jk})
-template <int N>
-__device__ __forceinline__ RowN<N> mm_nd(const RowN<N> &a, const RowN<N> &b, const Grp &g) {
-    RowN<N> c;
+// own rows of A B^+: (A B^+)_{ij} = sum_k A_{ik} conj(B_{jk})
+template <int N, int R>
+__device__ __forceinline__ Blk<N, R> mm_nd(const Blk<N, R> &a, const Blk<N, R> &b, const Grp &g) {
+    Blk<N, R> c;
 #pragma unroll
-    for (int j = 0; j < N; j++) {
-        const RowN<N> bj = row_from(b, g.base + j);
-        cx<double> s = {0.0, 0.0};
+    for (int q = 0; q < N / R; q++) {
+        const Blk<N, R> bq = blk_from<N, R>(b, g, q);
 #pragma unroll
-        for (int k = 0; k < N; k++) s = cmadd_nc(s, a.e[k], bj.e[k]);
-        c.e[j] = s;
+        for (int jj = 0; jj < R; jj++)
+#pragma unroll
+            for (int i = 0; i < R; i++) {
+                cx<double> s = {0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < N; k++) s = cmadd_nc(s, a.e[i][k], bq.e[jj][k]);
+                c.e[i][q * R + jj] = s;
+            }
     }
     return c;
 }
 
-// column r of A: col_k = A_{kr}
-template <int N>
-__device__ __forceinline__ RowN<N> column(const RowN<N> &a, const Grp &g) {
-    RowN<N> col;
+// columns of A at the own row indices: col_{ik} = A_{k, row(i)}
+template <int N, int R>
+__device__ __forceinline__ Blk<N, R> column(const Blk<N, R> &a, const Grp &g) {
+    Blk<N, R> col;
 #pragma unroll
-    for (int k = 0; k < N; k++) col.e[k] = pick(row_from(a, g.base + k), g.r);
+    for (int q = 0; q < N / R; q++) {
+        const Blk<N, R> aq = blk_from<N, R>(a, g, q);
+#pragma unroll
+        for (int kk = 0; kk < R; kk++)
+#pragma unroll
+            for (int i = 0; i < R; i++) {
+                if constexpr (N == R)
+                    col.e[i][q * R + kk] = aq.e[kk][i];
+                else
+                    col.e[i][q * R + kk] = pick<N>(aq.e[kk], row_index<N, R>(g, i));
+            }
+    }
     return col;
 }
 
-// row r of A^+ B: sum_k conj(A_{kr}) B_k
-template <int N>
-__device__ __forceinline__ RowN<N> mm_dn(const RowN<N> &a, const RowN<N> &b, const Grp &g) {
-    const RowN<N> col = column(a, g);
-    RowN<N> c = row_zero<N>();
+// own rows of A^+ B: sum_k conj(A_{k, row(i)}) B_k
+template <int N, int R>
+__device__ __forceinline__ Blk<N, R> mm_dn(const Blk<N, R> &a, const Blk<N, R> &b, const Grp &g) {
+    const Blk<N, R> col = column<N, R>(a, g);
+    Blk<N, R> c = blk_zero<N, R>();
 #pragma unroll
-    for (int k = 0; k < N; k++) {
-        const RowN<N> bk = row_from(b, g.base + k);
+    for (int q = 0; q < N / R; q++) {
+        const Blk<N, R> bq = blk_from<N, R>(b, g, q);
 #pragma unroll
-        for (int j = 0; j < N; j++) c.e[j] = cmadd_cn(c.e[j], col.e[k], bk.e[j]);
+        for (int kk = 0; kk < R; kk++)
+#pragma unroll
+            for (int i = 0; i < R; i++)
+#pragma unroll
+                for (int j = 0; j < N; j++)
+                    c.e[i][j] = cmadd_cn(c.e[i][j], col.e[i][q * R + kk], bq.e[kk][j]);
     }
     return c;
 }
 
-template <int N>
-__device__ __forceinline__ void row_axpy(RowN<N> &y, cx<double> z, const RowN<N> &x) {
+template <int N, int R>
+__device__ __forceinline__ void blk_axpy(Blk<N, R> &y, cx<double> z, const Blk<N, R> &x) {
 #pragma unroll
-    for (int j = 0; j < N; j++) y.e[j] = cmadd(y.e[j], z, x.e[j]);
+    for (int i = 0; i < R; i++)
+#pragma unroll
+        for (int j = 0; j < N; j++) y.e[i][j] = cmadd(y.e[i][j], z, x.e[i][j]);
 }
 
 // ---------------------------------------------------------------------------
-// storage access: row r of link (mu, site); the plane of mu is a uniform base,
-// the lane part a 32-bit byte offset (sites per configuration are capped so
-// that N^2 planes of one direction span less than 4 GiB)
+// storage access: the own rows of link (mu, site); the plane of mu is a uniform
+// base, the lane part a 32-bit byte offset (sites per configuration are capped
+// so that the N^2 planes of one direction span less than 4 GiB)
 
 template <int N>
 __device__ __forceinline__ unsigned row_off(int r, int j, int stride, int site) {
     return ((unsigned)(r * N + j) * (unsigned)stride + (unsigned)site) * 16u;
 }
 
-template <int N>
-__device__ __forceinline__ RowN<N> load_row(gptr<const v2<double>> W, int stride, int mu, int r,
-                                            int site) {
+template <int N, int R>
+__device__ __forceinline__ Blk<N, R> load_blk(gptr<const v2<double>> W, int stride, int mu,
+                                              const Grp &g, int site) {
     gptr<const v2<double>> q = W + (size_t)(mu * N * N) * stride;
-    RowN<N> o;
+    Blk<N, R> o;
 #pragma unroll
-    for (int j = 0; j < N; j++) o.e[j] = ld(q, row_off<N>(r, j, stride, site));
+    for (int i = 0; i < R; i++)
+#pragma unroll
+        for (int j = 0; j < N; j++)
+            o.e[i][j] = ld(q, row_off<N>(row_index<N, R>(g, i), j, stride, site));
     return o;
 }
 
-template <int N>
-__device__ __forceinline__ void store_row(gptr<v2<double>> W, int stride, int mu, int r, int site,
-                                          const RowN<N> &v) {
+template <int N, int R>
+__device__ __forceinline__ void store_blk(gptr<v2<double>> W, int stride, int mu, const Grp &g,
+                                          int site, const Blk<N, R> &v) {
     gptr<v2<double>> q = W + (size_t)(mu * N * N) * stride;
 #pragma unroll
-    for (int j = 0; j < N; j++) st(q, row_off<N>(r, j, stride, site), v.e[j]);
+    for (int i = 0; i < R; i++)
+#pragma unroll
+        for (int j = 0; j < N; j++) st(q, row_off<N>(row_index<N, R>(g, i), j, stride, site), v.e[i][j]);
 }
 
 // twist exponent n_{mu nu} (mod N, antisymmetric) and Z = exp(2 pi i n / N)
@@ -185,59 +240,66 @@ __device__ __forceinline__ cx<double> zphase(int t) {
 
 // Omega_MU(n) = U_MU(n) S, S the twisted staple sum (upper staples times
 // Z^*_{mu nu}(n), lower staples times Z_{mu nu}(n - nu))
-template <int N, int MU>
-__device__ __forceinline__ RowN<N> omega_row(gptr<const v2<double>> W, const CfgDesc &c,
-                                             const Geo &g, const Grp &gr, RowN<N> &U) {
-    const int st = c.stride, r = gr.r;
-    RowN<N> S = row_zero<N>();
+template <int N, int R, int MU>
+__device__ __forceinline__ Blk<N, R> omega_blk(gptr<const v2<double>> W, const CfgDesc &c,
+                                               const Geo &g, const Grp &gr, Blk<N, R> &U) {
+    const int st = c.stride;
+    Blk<N, R> S = blk_zero<N, R>();
     auto add_staples = [&](int nu) {
         const int k = tw_exp<N>(c, MU, nu);
         // upper: U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
-        RowN<N> t = mm_nd(load_row<N>(W, st, nu, r, g.i + g.up(MU)),
-                          load_row<N>(W, st, MU, r, g.i + g.up(nu)), gr);
-        t = mm_nd(t, load_row<N>(W, st, nu, r, g.i), gr);
+        Blk<N, R> t = mm_nd<N, R>(load_blk<N, R>(W, st, nu, gr, g.i + g.up(MU)),
+                                  load_blk<N, R>(W, st, MU, gr, g.i + g.up(nu)), gr);
+        t = mm_nd<N, R>(t, load_blk<N, R>(W, st, nu, gr, g.i), gr);
         cx<double> z = {1.0, 0.0};
         if (k && g.n(MU) == 0 && g.n(nu) == 0) z = cconj(zphase<N>(k));
-        row_axpy(S, z, t);
+        blk_axpy(S, z, t);
         // lower: (U_mu(n-nu) U_nu(n+mu-nu))^+ U_nu(n-nu)
         const int imn = g.i + g.dn(nu);
-        t = mm_nn(load_row<N>(W, st, MU, r, imn), load_row<N>(W, st, nu, r, imn + g.up(MU)), gr);
-        t = mm_dn(t, load_row<N>(W, st, nu, r, imn), gr);
+        t = mm_nn<N, R>(load_blk<N, R>(W, st, MU, gr, imn),
+                        load_blk<N, R>(W, st, nu, gr, imn + g.up(MU)), gr);
+        t = mm_dn<N, R>(t, load_blk<N, R>(W, st, nu, gr, imn), gr);
         z = {1.0, 0.0};
         if (k && g.n(MU) == 0 && g.back(nu) == 0) z = zphase<N>(k);
-        row_axpy(S, z, t);
+        blk_axpy(S, z, t);
     };
-    if constexpr (N == 3) {
+    if constexpr ((N == 3 && R == 1) || (N == 2 && R == 2)) {
 #pragma unroll
         for (int nu = 0; nu < 4; nu++)
             if (nu != MU) add_staples(nu);
     } else {
         // one direction at a time: unrolled, the loads of all six staples are
-        // live together and the kernel spills from N = 5 on (and N = 2 keeps
-        // two waves per SIMD this way)
+        // live together and the larger blocks spill
 #pragma unroll 1
         for (int nu = 0; nu < 4; nu++)
             if (nu != MU) add_staples(nu);
     }
-    U = load_row<N>(W, st, MU, r, g.i);
-    return mm_nn(U, S, gr);
+    U = load_blk<N, R>(W, st, MU, gr, g.i);
+    return mm_nn<N, R>(U, S, gr);
 }
 
-// scale * P_ah(M), row r
-template <int N>
-__device__ __forceinline__ RowN<N> proj_ah_row(const RowN<N> &m, const Grp &g, double scale) {
-    const RowN<N> col = column(m, g);   // col_j = M_{jr}; (M^+)_{rj} = conj(col_j)
-    RowN<N> a;
+// scale * P_ah(M), own rows
+template <int N, int R>
+__device__ __forceinline__ Blk<N, R> proj_ah_blk(const Blk<N, R> &m, const Grp &g, double scale) {
+    const Blk<N, R> col = column<N, R>(m, g);   // (M^+)_{ij} = conj(col_ij)
+    Blk<N, R> a;
+    double im = 0.0;
 #pragma unroll
-    for (int j = 0; j < N; j++)
-        a.e[j] = {0.5 * (m.e[j].x - col.e[j].x), 0.5 * (m.e[j].y + col.e[j].y)};
-    // the diagonal of (M - M^+)/2 is i Im M_rr; remove the trace part
-    const double t = group_sum<N>(pick(m, g.r).y, g) / (double)N;
+    for (int i = 0; i < R; i++) {
 #pragma unroll
-    for (int j = 0; j < N; j++) {
-        if (j == g.r) a.e[j].y -= t;
-        a.e[j] = {scale * a.e[j].x, scale * a.e[j].y};
+        for (int j = 0; j < N; j++)
+            a.e[i][j] = {0.5 * (m.e[i][j].x - col.e[i][j].x), 0.5 * (m.e[i][j].y + col.e[i][j].y)};
+        im += pick<N>(m.e[i], row_index<N, R>(g, i)).y;
     }
+    // the diagonal of (M - M^+)/2 is i Im M_rr; remove the trace part
+    const double t = group_sum<N, R>(im, g) / (double)N;
+#pragma unroll
+    for (int i = 0; i < R; i++)
+#pragma unroll
+        for (int j = 0; j < N; j++) {
+            if (j == row_index<N, R>(g, i)) a.e[i][j].y -= t;
+            a.e[i][j] = {scale * a.e[i][j].x, scale * a.e[i][j].y};
+        }
     return a;
 }
 
@@ -245,35 +307,40 @@ __device__ __forceinline__ RowN<N> proj_ah_row(const RowN<N> &m, const Grp &g, d
 // degree-12 Taylor polynomial by Horner's rule as T <- 1 + T Y / k (T is a
 // polynomial in Y, so T Y = Y T), then s squarings.  Truncation error
 // ||Y||^13 / 13! < 3e-18.
-template <int N>
-__device__ __forceinline__ RowN<N> exp_row(const RowN<N> &x, const Grp &g) {
+template <int N, int R>
+__device__ __forceinline__ Blk<N, R> exp_blk(const Blk<N, R> &x, const Grp &g) {
     double n2 = 0.0;
 #pragma unroll
-    for (int j = 0; j < N; j++) n2 = fma(x.e[j].x, x.e[j].x, fma(x.e[j].y, x.e[j].y, n2));
-    const double nrm = sqrt(group_sum<N>(n2, g));
+    for (int i = 0; i < R; i++)
+#pragma unroll
+        for (int j = 0; j < N; j++)
+            n2 = fma(x.e[i][j].x, x.e[i][j].x, fma(x.e[i][j].y, x.e[i][j].y, n2));
+    const double nrm = sqrt(group_sum<N, R>(n2, g));
     int s = 0;
     if (nrm > 0.25) s = (int)ceil(log2(nrm * 4.0));
     const double f = ldexp(1.0, -s);
-    RowN<N> y;
-#pragma unroll
-    for (int j = 0; j < N; j++) y.e[j] = {f * x.e[j].x, f * x.e[j].y};
     constexpr int M = 12;
-    RowN<N> t;
+    Blk<N, R> y, t;
 #pragma unroll
-    for (int j = 0; j < N; j++) {
-        t.e[j] = {y.e[j].x * (1.0 / M), y.e[j].y * (1.0 / M)};
-        if (j == g.r) t.e[j].x += 1.0;
-    }
-    for (int k = M - 1; k >= 1; k--) {
-        const RowN<N> ty = mm_nn(t, y, g);
-        const double ik = 1.0 / (double)k;
+    for (int i = 0; i < R; i++)
 #pragma unroll
         for (int j = 0; j < N; j++) {
-            t.e[j] = {ty.e[j].x * ik, ty.e[j].y * ik};
-            if (j == g.r) t.e[j].x += 1.0;
+            y.e[i][j] = {f * x.e[i][j].x, f * x.e[i][j].y};
+            t.e[i][j] = {y.e[i][j].x * (1.0 / M), y.e[i][j].y * (1.0 / M)};
+            if (j == row_index<N, R>(g, i)) t.e[i][j].x += 1.0;
         }
+    for (int k = M - 1; k >= 1; k--) {
+        const Blk<N, R> ty = mm_nn<N, R>(t, y, g);
+        const double ik = 1.0 / (double)k;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+#pragma unroll
+            for (int j = 0; j < N; j++) {
+                t.e[i][j] = {ty.e[i][j].x * ik, ty.e[i][j].y * ik};
+                if (j == row_index<N, R>(g, i)) t.e[i][j].x += 1.0;
+            }
     }
-    for (int i = 0; i < s; i++) t = mm_nn(t, t, g);
+    for (int i = 0; i < s; i++) t = mm_nn<N, R>(t, t, g);
     return t;
 }
 
@@ -290,7 +357,7 @@ struct SunStageArgs {
 __constant__ double kSunRkA[3] = {0.0, -17.0 / 9.0, -1.0};
 __constant__ double kSunRkB[3] = {0.25, 8.0 / 9.0, 0.75};
 
-template <int N, int MU>
+template <int N, int R, int MU>
 __device__ __forceinline__ void sun_link_update(const SunStageArgs &a, const CfgDesc &c, int site,
                                                 const Grp &gr) {
     const int in = (c.cur + 3 * a.step + a.stage) & 1;
@@ -299,40 +366,40 @@ __device__ __forceinline__ void sun_link_update(const SunStageArgs &a, const Cfg
     gptr<v2<double>> X = as_global<double>(c.X);
     const double eps = a.step < c.n_full ? a.eps : c.eps_last;
     const Geo g = make_geo(c, site);
-    RowN<N> U;
-    const RowN<N> om = omega_row<N, MU>(W, c, g, gr, U);
-    RowN<N> z = proj_ah_row(om, gr, -kSunRkB[a.stage] * eps);   // B eps F, F = -P_ah(Omega)
+    Blk<N, R> U;
+    const Blk<N, R> om = omega_blk<N, R, MU>(W, c, g, gr, U);
+    Blk<N, R> z = proj_ah_blk<N, R>(om, gr, -kSunRkB[a.stage] * eps);   // B eps F, F = -P_ah(Omega)
     if (a.stage > 0) {
-        const RowN<N> xo = load_row<N>(X, c.stride, MU, gr.r, site);
-        row_axpy(z, cx<double>{kSunRkA[a.stage], 0.0}, xo);
+        const Blk<N, R> xo = load_blk<N, R>(X, c.stride, MU, gr, site);
+        blk_axpy(z, cx<double>{kSunRkA[a.stage], 0.0}, xo);
     }
-    if (a.stage < 2) store_row<N>(X, c.stride, MU, gr.r, site, z);
-    const RowN<N> e = exp_row(z, gr);
-    store_row<N>(Wout, c.stride, MU, gr.r, site, mm_nn(e, U, gr));
+    if (a.stage < 2) store_blk<N, R>(X, c.stride, MU, gr, site, z);
+    const Blk<N, R> e = exp_blk<N, R>(z, gr);
+    store_blk<N, R>(Wout, c.stride, MU, gr, site, mm_nn<N, R>(e, U, gr));
 }
 
 // work-group = one tile of 64 sites; wave w updates direction w for the
-// tile's sites, G = 64 / N at a time (lane = g N + r)
-template <int N>
+// tile's sites, G = 64 / L at a time (lane = g L + l)
+template <int N, int R>
 __global__ __launch_bounds__(256) void sun_stage_kernel(SunStageArgs a) {
     const int tile = blockIdx.x;
     if (tile >= a.n_tiles) return;
     const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ci = find_cfg(a.tile_start, a.n_act, tile);
     const CfgDesc c = a.cfgs[ci];
-    constexpr int G = 64 / N;
+    constexpr int L = N / R, G = 64 / L;
     const int lane = threadIdx.x & 63;
-    const int g = lane / N;
-    const Grp gr{g * N, lane - g * N};
+    const int g = lane / L;
+    const Grp gr{g * L, lane - g * L};
     const int first = (tile - a.tile_start[ci]) * kTile;
     for (int s0 = 0; s0 < kTile; s0 += G) {
         const int site = first + s0 + g;
         if (g >= G || s0 + g >= kTile || site >= c.V) continue;
         switch (mu) {
-            case 0: sun_link_update<N, 0>(a, c, site, gr); break;
-            case 1: sun_link_update<N, 1>(a, c, site, gr); break;
-            case 2: sun_link_update<N, 2>(a, c, site, gr); break;
-            default: sun_link_update<N, 3>(a, c, site, gr); break;
+            case 0: sun_link_update<N, R, 0>(a, c, site, gr); break;
+            case 1: sun_link_update<N, R, 1>(a, c, site, gr); break;
+            case 2: sun_link_update<N, R, 2>(a, c, site, gr); break;
+            default: sun_link_update<N, R, 3>(a, c, site, gr); break;
         }
     }
 }
@@ -348,61 +415,66 @@ __device__ __forceinline__ cx<double> leaf_phase(const CfgDesc &c, int mu, int n
     return {1.0, 0.0};
 }
 
-// row r of G_{mu nu}(n); rp += Re of this lane's diagonal entry of Z^* P_{mu nu}(n)
-template <int N>
-__device__ __forceinline__ RowN<N> clover_row(gptr<const v2<double>> W, const CfgDesc &c,
-                                              const Geo &g, const Grp &gr, int mu, int nu,
-                                              double &rp) {
-    const int st = c.stride, r = gr.r;
+// own rows of G_{mu nu}(n); rp += Re of this lane's diagonal entries of Z^* P_{mu nu}(n)
+template <int N, int R>
+__device__ __forceinline__ Blk<N, R> clover_blk(gptr<const v2<double>> W, const CfgDesc &c,
+                                                const Geo &g, const Grp &gr, int mu, int nu,
+                                                double &rp) {
+    const int st = c.stride;
     const int i = g.i, ipm = g.i + g.up(mu), ipn = g.i + g.up(nu);
     const int imm = g.i + g.dn(mu), imn = g.i + g.dn(nu);
-    RowN<N> C = row_zero<N>();
+    Blk<N, R> C = blk_zero<N, R>();
     // leaf 1: U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
-    RowN<N> t = mm_nn(load_row<N>(W, st, mu, r, i), load_row<N>(W, st, nu, r, ipm), gr);
-    t = mm_nd(t, load_row<N>(W, st, mu, r, ipn), gr);
-    t = mm_nd(t, load_row<N>(W, st, nu, r, i), gr);
-    cx<double> z = leaf_phase<N>(c, mu, nu, g.n(mu), g.n(nu));
-    row_axpy(C, z, t);
-    rp += cmul(z, pick(t, r)).x;
+    Blk<N, R> t = mm_nn<N, R>(load_blk<N, R>(W, st, mu, gr, i), load_blk<N, R>(W, st, nu, gr, ipm), gr);
+    t = mm_nd<N, R>(t, load_blk<N, R>(W, st, mu, gr, ipn), gr);
+    t = mm_nd<N, R>(t, load_blk<N, R>(W, st, nu, gr, i), gr);
+    const cx<double> z = leaf_phase<N>(c, mu, nu, g.n(mu), g.n(nu));
+    blk_axpy(C, z, t);
+#pragma unroll
+    for (int r = 0; r < R; r++) rp += cmul(z, pick<N>(t.e[r], row_index<N, R>(gr, r))).x;
     // leaf 2: U_nu(n-nu)^+ U_mu(n-nu) U_nu(n+mu-nu) U_mu(n)^+
-    t = mm_dn(load_row<N>(W, st, nu, r, imn), load_row<N>(W, st, mu, r, imn), gr);
-    t = mm_nn(t, load_row<N>(W, st, nu, r, imn + g.up(mu)), gr);
-    t = mm_nd(t, load_row<N>(W, st, mu, r, i), gr);
-    row_axpy(C, leaf_phase<N>(c, mu, nu, g.n(mu), g.back(nu)), t);
+    t = mm_dn<N, R>(load_blk<N, R>(W, st, nu, gr, imn), load_blk<N, R>(W, st, mu, gr, imn), gr);
+    t = mm_nn<N, R>(t, load_blk<N, R>(W, st, nu, gr, imn + g.up(mu)), gr);
+    t = mm_nd<N, R>(t, load_blk<N, R>(W, st, mu, gr, i), gr);
+    blk_axpy(C, leaf_phase<N>(c, mu, nu, g.n(mu), g.back(nu)), t);
     // leaf 3: U_nu(n) U_mu(n+nu-mu)^+ U_nu(n-mu)^+ U_mu(n-mu)
-    t = mm_nd(load_row<N>(W, st, nu, r, i), load_row<N>(W, st, mu, r, ipn + g.dn(mu)), gr);
-    t = mm_nd(t, load_row<N>(W, st, nu, r, imm), gr);
-    t = mm_nn(t, load_row<N>(W, st, mu, r, imm), gr);
-    row_axpy(C, leaf_phase<N>(c, mu, nu, g.back(mu), g.n(nu)), t);
+    t = mm_nd<N, R>(load_blk<N, R>(W, st, nu, gr, i), load_blk<N, R>(W, st, mu, gr, ipn + g.dn(mu)), gr);
+    t = mm_nd<N, R>(t, load_blk<N, R>(W, st, nu, gr, imm), gr);
+    t = mm_nn<N, R>(t, load_blk<N, R>(W, st, mu, gr, imm), gr);
+    blk_axpy(C, leaf_phase<N>(c, mu, nu, g.back(mu), g.n(nu)), t);
     // leaf 4: (U_nu(n-mu-nu) U_mu(n-mu))^+ U_mu(n-mu-nu) U_nu(n-nu)
     const int imm_mn = imm + g.dn(nu);
-    t = mm_nn(load_row<N>(W, st, nu, r, imm_mn), load_row<N>(W, st, mu, r, imm), gr);
-    t = mm_dn(t, load_row<N>(W, st, mu, r, imm_mn), gr);
-    t = mm_nn(t, load_row<N>(W, st, nu, r, imn), gr);
-    row_axpy(C, leaf_phase<N>(c, mu, nu, g.back(mu), g.back(nu)), t);
-    // G = -(i/8)(C - C^+): row r of C - C^+ is C_r - conj(column r of C)
-    const RowN<N> col = column(C, gr);
-    RowN<N> G;
+    t = mm_nn<N, R>(load_blk<N, R>(W, st, nu, gr, imm_mn), load_blk<N, R>(W, st, mu, gr, imm), gr);
+    t = mm_dn<N, R>(t, load_blk<N, R>(W, st, mu, gr, imm_mn), gr);
+    t = mm_nn<N, R>(t, load_blk<N, R>(W, st, nu, gr, imn), gr);
+    blk_axpy(C, leaf_phase<N>(c, mu, nu, g.back(mu), g.back(nu)), t);
+    // G = -(i/8)(C - C^+): own rows of C - C^+ are C_i - conj(column i of C)
+    const Blk<N, R> col = column<N, R>(C, gr);
+    Blk<N, R> G;
 #pragma unroll
-    for (int j = 0; j < N; j++) {
-        const double wr = C.e[j].x - col.e[j].x, wi = C.e[j].y + col.e[j].y;
-        G.e[j] = {0.125 * wi, -0.125 * wr};
-    }
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int j = 0; j < N; j++) {
+            const double wr = C.e[r][j].x - col.e[r][j].x, wi = C.e[r][j].y + col.e[r][j].y;
+            G.e[r][j] = {0.125 * wi, -0.125 * wr};
+        }
     return G;
 }
 
-template <int N>
-__device__ __forceinline__ double herm_dot(const RowN<N> &a, const RowN<N> &b) {
+template <int N, int R>
+__device__ __forceinline__ double herm_dot(const Blk<N, R> &a, const Blk<N, R> &b) {
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < N; j++) s = fma(a.e[j].x, b.e[j].x, fma(a.e[j].y, b.e[j].y, s));
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int j = 0; j < N; j++) s = fma(a.e[r][j].x, b.e[r][j].x, fma(a.e[r][j].y, b.e[r][j].y, s));
     return s;
 }
 
 // this lane's share of e(n), q(n), the plaquette sum and the action density:
 // for Hermitian G, Tr(G_a G_b) = sum_{r,j} Re G_a,rj conj(G_b,rj), so every
-// lane adds its row and the wave sum completes the traces
-template <int N>
+// lane adds its rows and the wave sum completes the traces
+template <int N, int R>
 __device__ __forceinline__ void measure_site_n(gptr<const v2<double>> W, const CfgDesc &c,
                                                const Geo &g, const Grp &gr, double v[4]) {
     // the three dual plane pairs (01,23), (02,13), (03,12), one at a time
@@ -412,8 +484,8 @@ __device__ __forceinline__ void measure_site_n(gptr<const v2<double>> W, const C
         const int a1 = pr + 1;                         // planes (0, a1) and (b0, b1)
         const int b0 = pr == 2 ? 1 : (pr == 1 ? 1 : 2);
         const int b1 = pr == 0 ? 3 : (pr == 1 ? 3 : 2);
-        const RowN<N> Ga = clover_row<N>(W, c, g, gr, 0, a1, p);
-        const RowN<N> Gb = clover_row<N>(W, c, g, gr, b0, b1, p);
+        const Blk<N, R> Ga = clover_blk<N, R>(W, c, g, gr, 0, a1, p);
+        const Blk<N, R> Gb = clover_blk<N, R>(W, c, g, gr, b0, b1, p);
         e += herm_dot(Ga, Ga) + herm_dot(Gb, Gb);
         const double d = herm_dot(Ga, Gb);
         q += pr == 1 ? -d : d;
@@ -421,7 +493,7 @@ __device__ __forceinline__ void measure_site_n(gptr<const v2<double>> W, const C
     v[0] += e;
     v[1] += q * 0.025330295910584444;   // 1 / (4 pi^2)
     v[2] += p;
-    v[3] += 6.0 - p;   // each lane's share of sum_planes (N - Re Tr Z^* P)
+    v[3] += 6.0 * R - p;   // this lane's share of sum_planes (N - Re Tr Z^* P)
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -433,7 +505,7 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // work-group = one tile; wave w measures the tile's sites 16 w .. 16 w + 15,
 // G at a time; the per-tile sums go to partials[tile][0], slots 1, 2 are zero
 // (the layout of the SU(3) measurement, so the same reduction finishes it)
-template <int N>
+template <int N, int R>
 __global__ __launch_bounds__(256) void sun_measure_kernel(const CfgDesc *__restrict__ cfgs,
                                                           const int *__restrict__ tile_start,
                                                           int n_cfg, int n_tiles,
@@ -447,16 +519,16 @@ __global__ __launch_bounds__(256) void sun_measure_kernel(const CfgDesc *__restr
     const CfgDesc c = cfgs[ci];
     const int sel = buf_sel < 0 ? c.cur : ((c.cur + buf_sel) & 1);
     gptr<const v2<double>> W = as_global<double>((const void *)(sel ? c.W[1] : c.W[0]));
-    constexpr int G = 64 / N;
+    constexpr int L = N / R, G = 64 / L;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int g = lane / N;
-    const Grp gr{g * N, lane - g * N};
+    const int g = lane / L;
+    const Grp gr{g * L, lane - g * L};
     const int first = (tile - tile_start[ci]) * kTile + 16 * w;
     double v[4] = {0, 0, 0, 0};
     for (int s0 = 0; s0 < 16; s0 += G) {
         const int site = first + s0 + g;
         if (g >= G || s0 + g >= 16 || site >= c.V) continue;
-        measure_site_n<N>(W, c, make_geo(c, site), gr, v);
+        measure_site_n<N, R>(W, c, make_geo(c, site), gr, v);
     }
     __shared__ double red[4][4];
 #pragma unroll
@@ -580,53 +652,81 @@ __global__ __launch_bounds__(64) void sun_check_kernel(const void *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// launchers
+// launchers.  Rows per lane for each N, in variant order (variant 0 is the
+// default): the first entry is the fastest measured on the benchmark boxes.
 
-template <int N>
-static hipError_t stage_n(hipStream_t s, const SunStageArgs &a) {
-    hipLaunchKernelGGL(sun_stage_kernel<N>, dim3(a.n_tiles), dim3(256), 0, s, a);
+__host__ __device__ constexpr int sun_rows(int nc, int v) {
+    // N:         2        3        4                 5   6        7   8
+    return nc == 2 ? (v == 0 ? 2 : 1)
+         : nc == 3 ? (v == 0 ? 3 : 1)
+         : nc == 4 ? (v == 0 ? 2 : (v == 1 ? 1 : 4))
+         : nc == 6 ? (v == 0 ? 2 : 1)
+         : 1;
+}
+
+int sun_variant_count(int nc) {
+    switch (nc) {
+        case 2: case 3: case 6: return 2;
+        case 4: return 3;
+        case 5: case 7: case 8: return 1;
+        default: return 0;
+    }
+}
+
+int sun_rows_per_lane(int nc, int v) {
+    if (v < 0) v = 0;
+    if (v >= sun_variant_count(nc)) return 0;
+    return sun_rows(nc, v);
+}
+
+template <int N, int R>
+static hipError_t stage_nr(hipStream_t s, const SunStageArgs &a) {
+    hipLaunchKernelGGL((sun_stage_kernel<N, R>), dim3(a.n_tiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_stage_sun(int nc, hipStream_t s, const CfgDesc *cfgs, const int *tile_start,
-                            int n_act, int n_tiles, int step, int stage, double eps) {
+template <int N, int R>
+static hipError_t measure_nr(hipStream_t s, const CfgDesc *cfgs, const int *tile_start, int n_cfg,
+                             int n_tiles, const MeasSlot *slots, double *partials, int buf_sel) {
+    hipLaunchKernelGGL((sun_measure_kernel<N, R>), dim3(n_tiles), dim3(256), 0, s, cfgs,
+                       tile_start, n_cfg, n_tiles, slots, partials, buf_sel);
+    return hipGetLastError();
+}
+
+// F(N, R) for every (N, R) pair the variant table can name
+#define TGF_SUN_DISPATCH(F, ...)                                                  \
+    switch (nc * 16 + sun_rows_per_lane(nc, variant)) {                           \
+        case 2 * 16 + 1: return F<2, 1>(__VA_ARGS__);                             \
+        case 2 * 16 + 2: return F<2, 2>(__VA_ARGS__);                             \
+        case 3 * 16 + 1: return F<3, 1>(__VA_ARGS__);                             \
+        case 3 * 16 + 3: return F<3, 3>(__VA_ARGS__);                             \
+        case 4 * 16 + 1: return F<4, 1>(__VA_ARGS__);                             \
+        case 4 * 16 + 2: return F<4, 2>(__VA_ARGS__);                             \
+        case 4 * 16 + 4: return F<4, 4>(__VA_ARGS__);                             \
+        case 5 * 16 + 1: return F<5, 1>(__VA_ARGS__);                             \
+        case 6 * 16 + 1: return F<6, 1>(__VA_ARGS__);                             \
+        case 6 * 16 + 2: return F<6, 2>(__VA_ARGS__);                             \
+        case 7 * 16 + 1: return F<7, 1>(__VA_ARGS__);                             \
+        case 8 * 16 + 1: return F<8, 1>(__VA_ARGS__);                             \
+        default: return hipErrorInvalidValue;                                     \
+    }
+
+hipError_t launch_stage_sun(int nc, int variant, hipStream_t s, const CfgDesc *cfgs,
+                            const int *tile_start, int n_act, int n_tiles, int step, int stage,
+                            double eps) {
     if (n_tiles <= 0) return hipSuccess;
     const SunStageArgs a{cfgs, tile_start, n_act, n_tiles, step, stage, eps};
-    switch (nc) {
-        case 2: return stage_n<2>(s, a);
-        case 3: return stage_n<3>(s, a);
-        case 4: return stage_n<4>(s, a);
-        case 5: return stage_n<5>(s, a);
-        case 6: return stage_n<6>(s, a);
-        case 7: return stage_n<7>(s, a);
-        case 8: return stage_n<8>(s, a);
-        default: return hipErrorInvalidValue;
-    }
+    TGF_SUN_DISPATCH(stage_nr, s, a)
 }
 
-template <int N>
-static hipError_t measure_n(hipStream_t s, const CfgDesc *cfgs, const int *tile_start, int n_cfg,
-                            int n_tiles, const MeasSlot *slots, double *partials, int buf_sel) {
-    hipLaunchKernelGGL(sun_measure_kernel<N>, dim3(n_tiles), dim3(256), 0, s, cfgs, tile_start,
-                       n_cfg, n_tiles, slots, partials, buf_sel);
-    return hipGetLastError();
-}
-
-hipError_t launch_measure_sun(int nc, hipStream_t s, const CfgDesc *cfgs, const int *tile_start,
-                              int n_cfg, int n_tiles, const MeasSlot *slots, double *partials,
-                              int buf_sel) {
+hipError_t launch_measure_sun(int nc, int variant, hipStream_t s, const CfgDesc *cfgs,
+                              const int *tile_start, int n_cfg, int n_tiles, const MeasSlot *slots,
+                              double *partials, int buf_sel) {
     if (n_tiles <= 0) return hipSuccess;
-    switch (nc) {
-        case 2: return measure_n<2>(s, cfgs, tile_start, n_cfg, n_tiles, slots, partials, buf_sel);
-        case 3: return measure_n<3>(s, cfgs, tile_start, n_cfg, n_tiles, slots, partials, buf_sel);
-        case 4: return measure_n<4>(s, cfgs, tile_start, n_cfg, n_tiles, slots, partials, buf_sel);
-        case 5: return measure_n<5>(s, cfgs, tile_start, n_cfg, n_tiles, slots, partials, buf_sel);
-        case 6: return measure_n<6>(s, cfgs, tile_start, n_cfg, n_tiles, slots, partials, buf_sel);
-        case 7: return measure_n<7>(s, cfgs, tile_start, n_cfg, n_tiles, slots, partials, buf_sel);
-        case 8: return measure_n<8>(s, cfgs, tile_start, n_cfg, n_tiles, slots, partials, buf_sel);
-        default: return hipErrorInvalidValue;
-    }
+    TGF_SUN_DISPATCH(measure_nr, s, cfgs, tile_start, n_cfg, n_tiles, slots, partials, buf_sel)
 }
+
+#undef TGF_SUN_DISPATCH
 
 hipError_t launch_pack_sun(int nc, hipStream_t s, const void *src, void *W, int V, int stride) {
     const int nn = nc * nc;

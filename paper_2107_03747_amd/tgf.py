@@ -109,6 +109,8 @@ _sig = {
     "tgf_workspace_bytes_sun": (ctypes.c_size_t, [_I, _I, ctypes.POINTER(tgf_geom), _st]),
     "tgf_create_sun": (_st, [ctypes.POINTER(_P), _I, _I, ctypes.POINTER(tgf_geom), _st, _P,
                              ctypes.c_size_t, _P]),
+    "tgf_sun_variant_count": (_I, [_I]),
+    "tgf_sun_rows_per_lane": (_I, [_I, _I]),
     "tgf_load_links": (_st, [_P, _I, _P, ctypes.c_double]),
     "tgf_load_links_all": (_st, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double)]),
     "tgf_store_links": (_st, [_P, _I, _P]),

@@ -39,23 +39,31 @@ def _compare_rows(rows, ref, label):
 
 
 def _flow_both(N, dims_list, twists, starts, eps, t_end, meas_dt):
-    f = tgf.Flow([(d, t) for d, t in zip(dims_list, twists)], "f64", nc=N)
-    f.load_all([torch.from_numpy(s.copy()).cuda() for s in starts])
-    rows = f.flow(eps, t_end, meas_dt)
-    out = []
+    """Every stage variant (rows per lane) of SU(N) against the oracle."""
+    refs = []
     for k, (d, tw, s) in enumerate(zip(dims_list, twists, starts)):
         U = s.copy()
         ref = oracle.sun_flow(U, d, eps, t_end[k] if np.ndim(t_end) else t_end, meas_dt, twist=tw)
-        n = ref.shape[0]
-        _compare_rows(rows[:n, k], ref, f"SU({N}) {d} twist {tw[0]}")
-        got = f.store(k).cpu().numpy()
-        dl = np.abs(got - U).max()
-        print(f"    final links max |dU| {dl:.3g}", flush=True)
-        assert dl <= 1e-12
-        du, dd = f.unitarity(k)
-        assert du < 1e-13 and dd < 1e-13
-        out.append(U)
-    return f, out
+        refs.append((ref, U))
+    nv = tgf.tgf_sun_variant_count(N)
+    assert nv >= 1
+    for v in range(nv):
+        f = tgf.Flow([(d, t) for d, t in zip(dims_list, twists)], "f64", nc=N)
+        f.set_variant(v)
+        f.load_all([torch.from_numpy(s.copy()).cuda() for s in starts])
+        rows = f.flow(eps, t_end, meas_dt)
+        rpl = tgf.tgf_sun_rows_per_lane(N, v)
+        for k, (d, tw) in enumerate(zip(dims_list, twists)):
+            ref, U = refs[k]
+            n = ref.shape[0]
+            _compare_rows(rows[:n, k], ref, f"SU({N}) rows/lane {rpl} {d} twist {tw[0]}")
+            got = f.store(k).cpu().numpy()
+            dl = np.abs(got - U).max()
+            print(f"    final links max |dU| {dl:.3g}", flush=True)
+            assert dl <= 1e-12
+            du, dd = f.unitarity(k)
+            assert du < 1e-13 and dd < 1e-13
+    return [U for _, U in refs]
 
 
 @pytest.mark.parametrize("N,k", [(2, 1), (3, 1), (4, 1), (4, 3), (5, 2), (6, 1), (8, 3)])
@@ -133,9 +141,13 @@ def test_sun_errors():
         f.load(0, bad.cuda())
     assert e.value.status == tgf.TGF_E_NOT_SU3
     f.load(0, gen.near_identity_n(d, N, 0.5, seed=3).cuda())
-    for call in (lambda: f.mc(0.5, 1, 1), lambda: f.slice_charge(3), lambda: f.set_variant(0)):
+    for call in (lambda: f.mc(0.5, 1, 1), lambda: f.slice_charge(3)):
         with pytest.raises(tgf.TGFError) as e:
             call()
         assert e.value.status == tgf.TGF_E_UNSUPPORTED
-    f.autotune(None)                                               # nothing to tune
+    with pytest.raises(tgf.TGFError) as e:
+        f.set_variant(tgf.tgf_sun_variant_count(N))
+    assert e.value.status == tgf.TGF_E_INVAL
+    v = f.autotune(None)                                           # times the rows-per-lane variants
+    assert 0 <= v < tgf.tgf_sun_variant_count(N)
     f.set_variant(-1)
