@@ -95,10 +95,11 @@ def flops_per_site_stage(storage, variant, part=1):
     c12 = storage == "f32c12"
     upd = R2 if c12 else MM
     if variant.startswith("site_alg"):
-        # six two-row plaquettes projected to su(3) (r2_proj_ah ~35, +-accumulate 16),
-        # twelve lower staples (2 products each), four U S products + projection
-        return (18 * R2 + 6 * (35 + 16) + 28 * MM + 4 * 16 + 4 * (EXP + upd + XUPD)
-                + (REBUILD * 44 if c12 else 0))
+        # six two-row plaquettes projected to su(3) (r2_proj_ah ~55, +-accumulate 16),
+        # twelve lower staples (a product and an accumulated product, 2 MM + 18),
+        # four U S products + projection (16)
+        return (18 * R2 + 6 * (55 + 16) + 12 * (2 * MM + 18) + 4 * (MM + 16)
+                + 4 * (EXP + upd + XUPD) + (REBUILD * 44 if c12 else 0))
     if variant.startswith("site"):
         return 46 * MM + 4 * (EXP + upd + XUPD) + (REBUILD * 44 if c12 else 0)
     if variant.startswith("link"):
