@@ -35,20 +35,13 @@ template <class R, int NE>
 __device__ __forceinline__ void update_link_z(const Links<R, NE> &W, gptr<v2<R>> Wout,
                                               gptr<v2<R>> X, int stride, int mu, int i,
                                               Alg<R> Z, R a, int stage, int reunit) {
-    gptr<v2<R>> xp = X + (size_t)(mu * 4) * stride;
-    const unsigned u = lane_off<R>(i);
     if (stage > 0) {
+        R o[8];
+        ld_alg8<R>(X, mu, stride, i, o);
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            cx<R> o = ld(xp + (size_t)k * stride, u);
-            Z.a[2 * k] = fma(a, o.x, Z.a[2 * k]);
-            Z.a[2 * k + 1] = fma(a, o.y, Z.a[2 * k + 1]);
-        }
+        for (int k = 0; k < 8; k++) Z.a[k] = fma(a, o[k], Z.a[k]);
     }
-    if (stage < 2) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) st(xp + (size_t)k * stride, u, cx<R>{Z.a[2 * k], Z.a[2 * k + 1]});
-    }
+    if (stage < 2) st_alg8<R>(X, mu, stride, i, Z.a);
     M3<R> E = su3_exp<R, NE == 9 ? 3 : 2>(Z);
     M3<R> U = W(mu, i);
     M3<R> N;
@@ -330,22 +323,13 @@ __global__ __launch_bounds__(256) void plaq_alg_kernel(StageArgs a) {
             if (k && g.n(mu) == 0 && g.n(nu) == 0) r2_scale(P, cconj(omega_pow<R>(k)));
             R A8[8];
             r2_proj_ah(P, R(1), A8);
-            gptr<v2<R>> q = Ap + (size_t)(p * 4) * c.stride;
-#pragma unroll
-            for (int t = 0; t < 4; t++) st(q + (size_t)t * c.stride, u, cx<R>{A8[2 * t], A8[2 * t + 1]});
+            st_alg8<R>(Ap, p, c.stride, i, A8);
         }
 }
 
 template <class R>
 __device__ __forceinline__ void load_alg(gptr<const v2<R>> Ap, int stride, int p, int i, R out[8]) {
-    gptr<const v2<R>> q = Ap + (size_t)(p * 4) * stride;
-    const unsigned u = lane_off<R>(i);
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-        cx<R> v = ld(q + (size_t)t * stride, u);
-        out[2 * t] = v.x;
-        out[2 * t + 1] = v.y;
-    }
+    ld_alg8<R>(Ap, p, stride, i, out);
 }
 
 template <class R, int NE, int MU>
@@ -694,11 +678,10 @@ __global__ __launch_bounds__(256) void pack_kernel(const double2 *__restrict__ s
     const int mu = blockIdx.y;
     if (i >= V) return;
     const double2 *s = src + ((size_t)i * 4 + mu) * 9;
-    cx<R> *q = W + (size_t)(mu * NE) * stride + i;
 #pragma unroll
     for (int e = 0; e < NE; e++) {
         double2 v = s[e];
-        q[(size_t)e * stride] = cx<R>{(R)v.x, (R)v.y};
+        W[entry_index<R, NE>(mu, e, stride, i)] = cx<R>{(R)v.x, (R)v.y};
     }
 }
 
@@ -708,11 +691,10 @@ __global__ __launch_bounds__(256) void unpack_kernel(const cx<R> *__restrict__ W
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int mu = blockIdx.y;
     if (i >= V) return;
-    const cx<R> *q = W + (size_t)(mu * NE) * stride + i;
     M3<double> U;
 #pragma unroll
     for (int e = 0; e < NE; e++) {
-        cx<R> v = q[(size_t)e * stride];
+        cx<R> v = W[entry_index<R, NE>(mu, e, stride, i)];
         U.e[e / 3][e % 3] = {(double)v.x, (double)v.y};
     }
     if constexpr (NE == 6) rebuild_row2(U);
@@ -761,10 +743,10 @@ __global__ __launch_bounds__(256) void check_kernel(const void *__restrict__ src
 #pragma unroll
                 for (int e = 0; e < 9; e++) U.e[e / 3][e % 3] = {s[e].x, s[e].y};
             } else {
-                const cx<R> *q = (const cx<R> *)src + (size_t)(mu * NE) * stride + i;
+                const cx<R> *q = (const cx<R> *)src;
 #pragma unroll
                 for (int e = 0; e < NE; e++) {
-                    cx<R> v = q[(size_t)e * stride];
+                    cx<R> v = q[entry_index<R, NE>(mu, e, stride, i)];
                     U.e[e / 3][e % 3] = {(double)v.x, (double)v.y};
                 }
                 if constexpr (NE == 6) rebuild_row2(U);

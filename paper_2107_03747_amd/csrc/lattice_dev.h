@@ -162,22 +162,40 @@ struct Links {
     gptr<const v2<R>> p;
     int stride;
     __device__ __forceinline__ M3<R> operator()(int mu, int i) const {
-        // entry planes are uniform bases, the site index the lane offset
-        gptr<const v2<R>> q = p + (size_t)(mu * NE) * stride;
-        const unsigned u = lane_off<R>(i);
         M3<R> U;
-        U.e[0][0] = ld(q, u);
-        U.e[0][1] = ld(q + (size_t)stride, u);
-        U.e[0][2] = ld(q + (size_t)2 * stride, u);
-        U.e[1][0] = ld(q + (size_t)3 * stride, u);
-        U.e[1][1] = ld(q + (size_t)4 * stride, u);
-        U.e[1][2] = ld(q + (size_t)5 * stride, u);
-        if constexpr (NE == 9) {
-            U.e[2][0] = ld(q + (size_t)6 * stride, u);
-            U.e[2][1] = ld(q + (size_t)7 * stride, u);
-            U.e[2][2] = ld(q + (size_t)8 * stride, u);
-        } else {
+        if constexpr (NE == 6 && sizeof(R) == 4) {
+            // entry pairs: three 16-byte loads per link
+            typedef R R4 __attribute__((ext_vector_type(4)));
+            gptr<const char> q = (gptr<const char>)(p + (size_t)(mu * 6) * stride);
+            const unsigned u = (unsigned)i * 16u;
+            const size_t pl = (size_t)stride * 16u;
+            const R4 a = *(gptr<const R4>)(q + u);
+            const R4 b = *(gptr<const R4>)(q + pl + u);
+            const R4 c = *(gptr<const R4>)(q + 2 * pl + u);
+            U.e[0][0] = {a.x, a.y};
+            U.e[0][1] = {a.z, a.w};
+            U.e[0][2] = {b.x, b.y};
+            U.e[1][0] = {b.z, b.w};
+            U.e[1][1] = {c.x, c.y};
+            U.e[1][2] = {c.z, c.w};
             rebuild_row2(U);
+        } else {
+            // entry planes are uniform bases, the site index the lane offset
+            gptr<const v2<R>> q = p + (size_t)(mu * NE) * stride;
+            const unsigned u = lane_off<R>(i);
+            U.e[0][0] = ld(q, u);
+            U.e[0][1] = ld(q + (size_t)stride, u);
+            U.e[0][2] = ld(q + (size_t)2 * stride, u);
+            U.e[1][0] = ld(q + (size_t)3 * stride, u);
+            U.e[1][1] = ld(q + (size_t)4 * stride, u);
+            U.e[1][2] = ld(q + (size_t)5 * stride, u);
+            if constexpr (NE == 9) {
+                U.e[2][0] = ld(q + (size_t)6 * stride, u);
+                U.e[2][1] = ld(q + (size_t)7 * stride, u);
+                U.e[2][2] = ld(q + (size_t)8 * stride, u);
+            } else {
+                rebuild_row2(U);
+            }
         }
         return U;
     }
@@ -186,18 +204,80 @@ struct Links {
 template <class R, int NE>
 __device__ __forceinline__ void store_link(gptr<v2<R>> p, int stride, int mu, int i,
                                            const M3<R> &U) {
-    gptr<v2<R>> q = p + (size_t)(mu * NE) * stride;
-    const unsigned u = lane_off<R>(i);
-    st(q, u, U.e[0][0]);
-    st(q + (size_t)stride, u, U.e[0][1]);
-    st(q + (size_t)2 * stride, u, U.e[0][2]);
-    st(q + (size_t)3 * stride, u, U.e[1][0]);
-    st(q + (size_t)4 * stride, u, U.e[1][1]);
-    st(q + (size_t)5 * stride, u, U.e[1][2]);
-    if constexpr (NE == 9) {
-        st(q + (size_t)6 * stride, u, U.e[2][0]);
-        st(q + (size_t)7 * stride, u, U.e[2][1]);
-        st(q + (size_t)8 * stride, u, U.e[2][2]);
+    if constexpr (NE == 6 && sizeof(R) == 4) {
+        typedef R R4 __attribute__((ext_vector_type(4)));
+        gptr<char> q = (gptr<char>)(p + (size_t)(mu * 6) * stride);
+        const unsigned u = (unsigned)i * 16u;
+        const size_t pl = (size_t)stride * 16u;
+        R4 a, b, c;
+        a.x = U.e[0][0].x; a.y = U.e[0][0].y; a.z = U.e[0][1].x; a.w = U.e[0][1].y;
+        b.x = U.e[0][2].x; b.y = U.e[0][2].y; b.z = U.e[1][0].x; b.w = U.e[1][0].y;
+        c.x = U.e[1][1].x; c.y = U.e[1][1].y; c.z = U.e[1][2].x; c.w = U.e[1][2].y;
+        *(gptr<R4>)(q + u) = a;
+        *(gptr<R4>)(q + pl + u) = b;
+        *(gptr<R4>)(q + 2 * pl + u) = c;
+        return;
+    } else {
+        gptr<v2<R>> q = p + (size_t)(mu * NE) * stride;
+        const unsigned u = lane_off<R>(i);
+        st(q, u, U.e[0][0]);
+        st(q + (size_t)stride, u, U.e[0][1]);
+        st(q + (size_t)2 * stride, u, U.e[0][2]);
+        st(q + (size_t)3 * stride, u, U.e[1][0]);
+        st(q + (size_t)4 * stride, u, U.e[1][1]);
+        st(q + (size_t)5 * stride, u, U.e[1][2]);
+        if constexpr (NE == 9) {
+            st(q + (size_t)6 * stride, u, U.e[2][0]);
+            st(q + (size_t)7 * stride, u, U.e[2][1]);
+            st(q + (size_t)8 * stride, u, U.e[2][2]);
+        }
+    }
+}
+
+// The 8 reals of an su(3) element in a buffer of records [record][4 complex]
+// [site] (the RK accumulator X, the plaquette algebra A).  FP32 pairs the
+// complex slots, [record][2][site][4 reals], so the record moves with two
+// 16-byte accesses; FP64 keeps four 16-byte planes.
+template <class R>
+__device__ __forceinline__ void ld_alg8(gptr<const v2<R>> base, int rec, int stride, int i,
+                                        R out[8]) {
+    if constexpr (sizeof(R) == 4) {
+        typedef R R4 __attribute__((ext_vector_type(4)));
+        gptr<const char> q = (gptr<const char>)(base + (size_t)(rec * 4) * stride);
+        const unsigned u = (unsigned)i * 16u;
+        const R4 a = *(gptr<const R4>)(q + u);
+        const R4 b = *(gptr<const R4>)(q + (size_t)stride * 16u + u);
+        out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+        out[4] = b.x; out[5] = b.y; out[6] = b.z; out[7] = b.w;
+    } else {
+        gptr<const v2<R>> q = base + (size_t)(rec * 4) * stride;
+        const unsigned u = lane_off<R>(i);
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const cx<R> v = ld(q + (size_t)t * stride, u);
+            out[2 * t] = v.x;
+            out[2 * t + 1] = v.y;
+        }
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void st_alg8(gptr<v2<R>> base, int rec, int stride, int i,
+                                        const R v[8]) {
+    if constexpr (sizeof(R) == 4) {
+        typedef R R4 __attribute__((ext_vector_type(4)));
+        gptr<char> q = (gptr<char>)(base + (size_t)(rec * 4) * stride);
+        const unsigned u = (unsigned)i * 16u;
+        R4 a, b;
+        a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
+        b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
+        *(gptr<R4>)(q + u) = a;
+        *(gptr<R4>)(q + (size_t)stride * 16u + u) = b;
+    } else {
+        gptr<v2<R>> q = base + (size_t)(rec * 4) * stride;
+        const unsigned u = lane_off<R>(i);
+#pragma unroll
+        for (int t = 0; t < 4; t++) st(q + (size_t)t * stride, u, cx<R>{v[2 * t], v[2 * t + 1]});
     }
 }
 
