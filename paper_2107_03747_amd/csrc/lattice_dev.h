@@ -163,10 +163,11 @@ struct Links {
     int stride;
     __device__ __forceinline__ M3<R> operator()(int mu, int i) const {
         M3<R> U;
-        if constexpr (NE == 6 && sizeof(R) == 4) {
-            // entry pairs: three 16-byte loads per link
+        if constexpr (sizeof(R) == 4) {
+            // entry pairs: three (12-real) or four 16-byte loads, and for the
+            // full storage entry 8 alone (entry_index)
             typedef R R4 __attribute__((ext_vector_type(4)));
-            gptr<const char> q = (gptr<const char>)(p + (size_t)(mu * 6) * stride);
+            gptr<const char> q = (gptr<const char>)(p + (size_t)(mu * NE) * stride);
             const unsigned u = (unsigned)i * 16u;
             const size_t pl = (size_t)stride * 16u;
             const R4 a = *(gptr<const R4>)(q + u);
@@ -178,7 +179,14 @@ struct Links {
             U.e[1][0] = {b.z, b.w};
             U.e[1][1] = {c.x, c.y};
             U.e[1][2] = {c.z, c.w};
-            rebuild_row2(U);
+            if constexpr (NE == 9) {
+                const R4 d = *(gptr<const R4>)(q + 3 * pl + u);
+                U.e[2][0] = {d.x, d.y};
+                U.e[2][1] = {d.z, d.w};
+                U.e[2][2] = ld(p + (size_t)(mu * 9 + 8) * stride, lane_off<R>(i));
+            } else {
+                rebuild_row2(U);
+            }
         } else {
             // entry planes are uniform bases, the site index the lane offset
             gptr<const v2<R>> q = p + (size_t)(mu * NE) * stride;
@@ -204,9 +212,9 @@ struct Links {
 template <class R, int NE>
 __device__ __forceinline__ void store_link(gptr<v2<R>> p, int stride, int mu, int i,
                                            const M3<R> &U) {
-    if constexpr (NE == 6 && sizeof(R) == 4) {
+    if constexpr (sizeof(R) == 4) {
         typedef R R4 __attribute__((ext_vector_type(4)));
-        gptr<char> q = (gptr<char>)(p + (size_t)(mu * 6) * stride);
+        gptr<char> q = (gptr<char>)(p + (size_t)(mu * NE) * stride);
         const unsigned u = (unsigned)i * 16u;
         const size_t pl = (size_t)stride * 16u;
         R4 a, b, c;
@@ -216,6 +224,12 @@ __device__ __forceinline__ void store_link(gptr<v2<R>> p, int stride, int mu, in
         *(gptr<R4>)(q + u) = a;
         *(gptr<R4>)(q + pl + u) = b;
         *(gptr<R4>)(q + 2 * pl + u) = c;
+        if constexpr (NE == 9) {
+            R4 d;
+            d.x = U.e[2][0].x; d.y = U.e[2][0].y; d.z = U.e[2][1].x; d.w = U.e[2][1].y;
+            *(gptr<R4>)(q + 3 * pl + u) = d;
+            st(p + (size_t)(mu * 9 + 8) * stride, lane_off<R>(i), U.e[2][2]);
+        }
         return;
     } else {
         gptr<v2<R>> q = p + (size_t)(mu * NE) * stride;

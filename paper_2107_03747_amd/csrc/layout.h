@@ -4,9 +4,10 @@
 //   W[0], W[1]  ping-pong link buffers, structure of arrays
 //               [mu (4)][entry (NE)][site (stride)] of complex R, where NE = 9
 //               (full storage, row-major entries) or 6 (rows 0 and 1 only);
-//               the FP32 12-real storage pairs the entries, [mu][pair (3)]
-//               [site][2], so that one 16-byte access moves two complex
-//               numbers (entry_index);
+//               FP32 pairs the entries, [mu][pair][site][2] (12-real: 3
+//               pairs; full: 4 pairs and entry 8 alone, [mu][8][site]), so
+//               that one 16-byte access moves two complex numbers
+//               (entry_index);
 //   X           RK accumulator [mu (4)][slot (4)][site (stride)] of complex R:
 //               slots 0..2 = X01, X02, X12, slot 3 = (Im X00, Im X11);
 //   A           plaquette algebra [plane (6)][slot (4)][site (stride)] of
@@ -49,8 +50,10 @@ struct CfgDesc {
 // Index (in complex elements) of entry e of link (mu, site i) in a link buffer.
 template <class R, int NE>
 __host__ __device__ inline size_t entry_index(int mu, int e, int stride, int i) {
-    if (NE == 6 && sizeof(R) == 4)
-        return (((size_t)(mu * 3 + (e >> 1)) * stride + i) << 1) + (e & 1);
+    if (sizeof(R) == 4 && e < 8) {
+        const size_t base = (size_t)(mu * NE) * stride;   // direction mu starts here
+        return base + (((size_t)(e >> 1) * stride + i) << 1) + (e & 1);
+    }
     return (size_t)(mu * NE + e) * stride + i;
 }
 
