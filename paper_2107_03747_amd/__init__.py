@@ -10,7 +10,7 @@ __all__ = ["gen", "tgf"]
 
 
 def __getattr__(name):
-    if name in ("gen", "tgf"):
+    if name in ("gen", "tgf", "build"):
         import importlib
         return importlib.import_module(f"{__name__}.{name}")
     from . import tgf as _tgf
