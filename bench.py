@@ -95,11 +95,19 @@ def flops_per_site_stage(storage, variant, part=1):
     c12 = storage == "f32c12"
     upd = R2 if c12 else MM
     if variant.startswith("site_alg"):
-        # six two-row plaquettes projected to su(3) (r2_proj_ah ~55, +-accumulate 16),
-        # twelve lower staples (a product and an accumulated product, 2 MM + 18),
-        # four U S products + projection (16)
-        return (18 * R2 + 6 * (55 + 16) + 12 * (2 * MM + 18) + 4 * (MM + 16)
-                + 4 * (EXP + upd + XUPD) + (REBUILD * 44 if c12 else 0))
+        if storage == "f64":
+            # six two-row plaquettes projected to su(3) (r2_proj_ah ~55, +-accumulate 16),
+            # twelve lower staples (a product and an accumulated product, 2 MM + 18),
+            # four U S products + projection (16)
+            return (18 * R2 + 6 * (55 + 16) + 12 * (2 * MM + 18) + 4 * (MM + 16)
+                    + 4 * (EXP + upd + XUPD))
+        # FP32: six upper plaquettes and twelve lower closed loops, three two-row
+        # products each, projected (55) and accumulated (16 for the two links of an
+        # upper plaquette, 8 for a lower loop); 12-real storage rebuilds the third
+        # row of every non-leading factor (15 in the upper plaquettes, where each
+        # own link is rebuilt once, and 36 in the lower loops)
+        return (54 * R2 + 6 * (55 + 16) + 12 * (55 + 8) + 4 * (EXP + upd + XUPD)
+                + (REBUILD * 51 if c12 else 0))
     if variant.startswith("site"):
         return 46 * MM + 4 * (EXP + upd + XUPD) + (REBUILD * 44 if c12 else 0)
     if variant.startswith("link"):

@@ -147,25 +147,55 @@ __global__ __launch_bounds__(256) void stage_site_kernel(StageArgs a) {
 // Site variant with su(3) force accumulators.  P_ah is linear and
 // P_ah(P^+) = -P_ah(P), so each upper plaquette Z^* P_{mu nu}(n) enters its two
 // links as +-P_ah in the 8-real form, taken from its two computed rows
-// (r2_proj_ah, no third row); only the lower staples are summed as 3x3
-// matrices and multiplied by U_mu(n).  The four force accumulators take
-// 4 x 8 reals instead of 4 x 18.
+// (r2_proj_ah, no third row).  The four force accumulators take 4 x 8 reals
+// instead of 4 x 18.  Lower staples: FP32 forms each closed loop U_mu(n) x
+// staple in two rows and projects it the same way (fewer operations, no 3x3
+// sum, 188 instead of 240 registers); FP64 sums the three staples as 3x3
+// matrices and multiplies the sum by U_mu(n) once, which runs 1.5% faster at
+// its one wave per SIMD.
 template <class R, int NE, int MU>
 __device__ __forceinline__ void site_alg_update(const Links<R, NE> &W, gptr<v2<R>> Wout,
                                                 gptr<v2<R>> X, const CfgDesc &c, const Geo &g,
                                                 const Alg<R> &f, R beps, R ac,
                                                 const StageArgs &a) {
-    M3<R> S;
-    m_zero(S);
-#pragma unroll
-    for (int nu = 0; nu < 4; nu++) {
-        if (nu == MU) continue;
-        acc_lower_staple(S, W, c, g, MU, nu);
-    }
-    const Alg<R> lo = proj_ah(mul_nn(W(MU, g.i), S), R(1));
     Alg<R> Z;
+    if constexpr (sizeof(R) == 4) {
+        Z = f;
 #pragma unroll
-    for (int k = 0; k < 8; k++) Z.a[k] = -beps * (f.a[k] + lo.a[k]);
+        for (int nu = 0; nu < 4; nu++) {
+            if (nu == MU) continue;
+            // U_mu(n) times the lower staple is the closed loop
+            // U_mu(n) U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu), an SU(3) matrix
+            // times a cube root of unity: two rows, projected like the upper
+            // plaquettes
+            const int imn = g.i + g.dn(nu);
+            R2<R> P = r2_of(W(MU, g.i));
+            P = r2_mul_nd(P, W(nu, imn + g.up(MU)));
+            P = r2_mul_nd(P, W(MU, imn));
+            P = r2_mul_nn(P, W(nu, imn));
+            const int k = twist_exp(c, MU, nu);
+            // the loop is U_nu(n-nu)^+ P_{mu nu}(n-nu)^+ U_nu(n-nu): its factor is
+            // Z_{mu nu}, the conjugate of the Z^* on the plaquette
+            if (k && g.n(MU) == 0 && g.back(nu) == 0) r2_scale(P, omega_pow<R>(k));
+            R A8[8];
+            r2_proj_ah(P, R(1), A8);
+#pragma unroll
+            for (int t = 0; t < 8; t++) Z.a[t] += A8[t];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k++) Z.a[k] *= -beps;
+    } else {
+        M3<R> S;
+        m_zero(S);
+#pragma unroll
+        for (int nu = 0; nu < 4; nu++) {
+            if (nu == MU) continue;
+            acc_lower_staple(S, W, c, g, MU, nu);
+        }
+        const Alg<R> lo = proj_ah(mul_nn(W(MU, g.i), S), R(1));
+#pragma unroll
+        for (int k = 0; k < 8; k++) Z.a[k] = -beps * (f.a[k] + lo.a[k]);
+    }
     update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, a.reunit);
 }
 
