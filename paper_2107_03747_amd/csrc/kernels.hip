@@ -31,8 +31,8 @@ namespace tgf {
 
 // RK stage tail for one link, from Z = B eps F in the 8-real form:
 // X = Z + A X_old; W_out = exp(X) W_in.
-template <class R, int NE>
-__device__ __forceinline__ void update_link_z(const Links<R, NE> &W, gptr<v2<R>> Wout,
+template <class R, int NE, class LK>
+__device__ __forceinline__ void update_link_z(const LK &W, gptr<v2<R>> Wout,
                                               gptr<v2<R>> X, int stride, int mu, int i,
                                               Alg<R> Z, R a, int stage, int reunit) {
     if (stage > 0) {
@@ -153,8 +153,8 @@ __global__ __launch_bounds__(256) void stage_site_kernel(StageArgs a) {
 // sum, 188 instead of 240 registers); FP64 sums the three staples as 3x3
 // matrices and multiplies the sum by U_mu(n) once, which runs 1.5% faster at
 // its one wave per SIMD.
-template <class R, int NE, int MU>
-__device__ __forceinline__ void site_alg_update(const Links<R, NE> &W, gptr<v2<R>> Wout,
+template <class R, int NE, int MU, class LK>
+__device__ __forceinline__ void site_alg_update(const LK &W, gptr<v2<R>> Wout,
                                                 gptr<v2<R>> X, const CfgDesc &c, const Geo &g,
                                                 const Alg<R> &f, R beps, R ac,
                                                 const StageArgs &a) {
@@ -199,27 +199,13 @@ __device__ __forceinline__ void site_alg_update(const Links<R, NE> &W, gptr<v2<R
     update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, a.reunit);
 }
 
-template <class R, int NE>
-__device__ __forceinline__ void site_alg_body(const StageArgs &a) {
-    const int nb = (a.n_tiles + 3) >> 2;
-    const int b = remap_block(blockIdx.x, nb, a.xcd);
-    if (b >= nb) return;
-    const int tile = b * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (tile >= a.n_tiles) return;
-    const int ci = find_cfg(a.tile_start, a.n_act, tile);
-    const CfgDesc c = a.cfgs[ci];
-    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
-    if (i >= c.V) return;
-
-    const int in = (c.cur + 3 * a.step + a.stage) & 1;
-    const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
-    gptr<v2<R>> Wout = as_global<R>(in ? c.W[0] : c.W[1]);
-    gptr<v2<R>> X = as_global<R>(c.X);
-    const double eps = a.step < c.n_full ? a.eps : c.eps_last;
-    const R beps = (R)(kRkB[a.stage] * eps);
-    const R ac = (R)kRkA[a.stage];
-    const Geo g = make_geo(c, i);
-
+// The force of the four links of site g.i from su(3) accumulators, then the
+// four RK updates; W is the link accessor (global memory, or LDS-staged).
+template <class R, int NE, class LK>
+__device__ __forceinline__ void site_alg_work(const LK &W, gptr<v2<R>> Wout, gptr<v2<R>> X,
+                                              const CfgDesc &c, const Geo &g, R beps, R ac,
+                                              const StageArgs &a) {
+    const int i = g.i;
     Alg<R> f[4];
 #pragma unroll
     for (int mu = 0; mu < 4; mu++)
@@ -249,6 +235,145 @@ __device__ __forceinline__ void site_alg_body(const StageArgs &a) {
     site_alg_update<R, NE, 1>(W, Wout, X, c, g, f[1], beps, ac, a);
     site_alg_update<R, NE, 2>(W, Wout, X, c, g, f[2], beps, ac, a);
     site_alg_update<R, NE, 3>(W, Wout, X, c, g, f[3], beps, ac, a);
+}
+
+template <class R, int NE>
+__device__ __forceinline__ void site_alg_body(const StageArgs &a) {
+    const int nb = (a.n_tiles + 3) >> 2;
+    const int b = remap_block(blockIdx.x, nb, a.xcd);
+    if (b >= nb) return;
+    const int tile = b * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= a.n_tiles) return;
+    const int ci = find_cfg(a.tile_start, a.n_act, tile);
+    const CfgDesc c = a.cfgs[ci];
+    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
+    if (i >= c.V) return;
+
+    const int in = (c.cur + 3 * a.step + a.stage) & 1;
+    const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
+    gptr<v2<R>> Wout = as_global<R>(in ? c.W[0] : c.W[1]);
+    gptr<v2<R>> X = as_global<R>(c.X);
+    const double eps = a.step < c.n_full ? a.eps : c.eps_last;
+    const R beps = (R)(kRkB[a.stage] * eps);
+    const R ac = (R)kRkA[a.stage];
+    site_alg_work<R, NE>(W, Wout, X, c, make_geo(c, i), beps, ac, a);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged site variant.  A work-group owns 256 consecutive sites of one
+// configuration; it first copies their four links into LDS as 16-byte units
+// ([mu][unit][site]: FP32 entry pairs, and entry 8 alone for the full
+// storage; FP64 one complex entry per unit), then every link a wave needs is
+// read from LDS when all of its active lanes find the link's site inside the
+// block, and from global memory otherwise.  With the site order n0 fastest,
+// the block holds whole (n0, n1) planes when l^2 divides 256, so the
+// neighbours in directions 0 and 1, and most of those in direction 2, come
+// from LDS.  LDS per work-group: 48 KB (FP32 12-real), 72 KB (FP32 full),
+// 144 KB (FP64).  (Staging full matrices for the 12-real storage, so that
+// its third rows are rebuilt once per link, ran 15% slower.)
+
+template <class R, int NE>
+struct StagedLinks {
+    typedef R U16 __attribute__((ext_vector_type(16 / sizeof(R))));
+    static constexpr int NU = sizeof(R) == 8 ? NE : (NE == 9 ? 4 : 3);   // units per link
+    Links<R, NE> gl;
+    const U16 *s16;           // [mu][unit][kBlock]
+    const v2<R> *s8;          // [mu][kBlock], FP32 full storage entry 8
+    int base;                 // first site of the block
+    int staged;               // work-group uniform
+    __device__ __forceinline__ M3<R> operator()(int mu, int j) const {
+        const unsigned k = (unsigned)(j - base);
+        if (staged && __all(k < (unsigned)kBlock)) {
+            const U16 *q = s16 + mu * NU * kBlock + k;
+            M3<R> U;
+            if constexpr (sizeof(R) == 4) {
+                const U16 a = q[0], b = q[kBlock], c = q[2 * kBlock];
+                U.e[0][0] = {a.x, a.y};
+                U.e[0][1] = {a.z, a.w};
+                U.e[0][2] = {b.x, b.y};
+                U.e[1][0] = {b.z, b.w};
+                U.e[1][1] = {c.x, c.y};
+                U.e[1][2] = {c.z, c.w};
+                if constexpr (NE == 9) {
+                    const U16 d = q[3 * kBlock];
+                    U.e[2][0] = {d.x, d.y};
+                    U.e[2][1] = {d.z, d.w};
+                    const v2<R> z = s8[mu * kBlock + k];
+                    U.e[2][2] = {z.x, z.y};
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < NE; e++) {
+                    const U16 v = q[e * kBlock];
+                    U.e[e / 3][e % 3] = {v.x, v.y};
+                }
+            }
+            if constexpr (NE == 6) rebuild_row2(U);
+            return U;
+        }
+        return gl(mu, j);
+    }
+};
+
+template <class R, int NE>
+__device__ __forceinline__ void site_lds_body(const StageArgs &a) {
+    typedef typename StagedLinks<R, NE>::U16 U16;
+    constexpr int NU = StagedLinks<R, NE>::NU;
+    constexpr bool kE8 = sizeof(R) == 4 && NE == 9;
+    __shared__ U16 s16[4 * NU * kBlock];
+    __shared__ v2<R> s8[kE8 ? 4 * kBlock : 1];
+
+    const int nb = (a.n_tiles + 3) >> 2;
+    const int b = remap_block(blockIdx.x, nb, a.xcd);
+    if (b >= nb) return;                                   // whole work-group
+    const int t0 = b * 4;
+    const int tile = t0 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // stage only when the four tiles exist and belong to one configuration
+    // (work-group uniform, so every wave reaches the barrier below)
+    const int ci0 = find_cfg(a.tile_start, a.n_act, t0);
+    const int staged = t0 + 3 < a.n_tiles && find_cfg(a.tile_start, a.n_act, t0 + 3) == ci0;
+    if (!staged && tile >= a.n_tiles) return;
+    const int ci = staged ? ci0 : find_cfg(a.tile_start, a.n_act, tile);
+    const CfgDesc c = a.cfgs[ci];
+    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
+
+    const int in = (c.cur + 3 * a.step + a.stage) & 1;
+    const Links<R, NE> G{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
+    if (staged) {
+        if (i < c.V) {
+            // unit u of link (mu, i) sits at byte (mu NE stride 2 sizeof(R)) +
+            // u stride 16 + 16 i (the FP32 pairs of entry_index; FP64 entries)
+            gptr<const char> q = (gptr<const char>)G.p;
+            const size_t pl = (size_t)c.stride * 16u;
+            const unsigned u = (unsigned)i * 16u;
+#pragma unroll
+            for (int mu = 0; mu < 4; mu++) {
+                gptr<const char> qm = q + (size_t)(mu * NE) * c.stride * (2 * sizeof(R));
+#pragma unroll
+                for (int e = 0; e < NU; e++)
+                    s16[(mu * NU + e) * kBlock + threadIdx.x] = *(gptr<const U16>)(qm + e * pl + u);
+                if constexpr (kE8) {
+                    const cx<R> z = ld(G.p + (size_t)(mu * 9 + 8) * c.stride, lane_off<R>(i));
+                    s8[mu * kBlock + threadIdx.x] = v2<R>{z.x, z.y};
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (i >= c.V) return;
+
+    const StagedLinks<R, NE> W{G, s16, s8, (t0 - a.tile_start[ci]) * kTile, staged};
+    gptr<v2<R>> Wout = as_global<R>(in ? c.W[0] : c.W[1]);
+    gptr<v2<R>> X = as_global<R>(c.X);
+    const double eps = a.step < c.n_full ? a.eps : c.eps_last;
+    const R beps = (R)(kRkB[a.stage] * eps);
+    const R ac = (R)kRkA[a.stage];
+    site_alg_work<R, NE>(W, Wout, X, c, make_geo(c, i), beps, ac, a);
+}
+
+template <class R, int NE>
+__global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1) void stage_site_lds_kernel(StageArgs a) {
+    site_lds_body<R, NE>(a);
 }
 
 // Register budgets: FP64 keeps the whole working set in 512 registers (one
@@ -842,6 +967,8 @@ const char *variant_name(int v) {
         case V_SITE_ALG_XCD: return "site_alg_xcd";
         case V_SITE_ALG3: return "site_alg3";
         case V_SITE_ALG3_XCD: return "site_alg3_xcd";
+        case V_SITE_LDS: return "site_lds";
+        case V_SITE_LDS_XCD: return "site_lds_xcd";
         default: return "?";
     }
 }
@@ -849,7 +976,8 @@ const char *variant_name(int v) {
 template <class R, int NE>
 static hipError_t launch_stage_t(int variant, int part, hipStream_t s, const StageArgs &a) {
     const bool xcd = variant == V_SITE_XCD || variant == V_LINK_XCD || variant == V_SPLIT_XCD ||
-                     variant == V_SITE_ALG_XCD || variant == V_SITE_ALG3_XCD;
+                     variant == V_SITE_ALG_XCD || variant == V_SITE_ALG3_XCD ||
+                     variant == V_SITE_LDS_XCD;
     StageArgs b = a;
     b.xcd = xcd ? 1 : 0;
     const int site_blocks = xcd ? ((a.n_tiles + 3) / 4 + 7) / 8 * 8 : (a.n_tiles + 3) / 4;
@@ -871,6 +999,8 @@ static hipError_t launch_stage_t(int variant, int part, hipStream_t s, const Sta
                                b);
     } else if (variant == V_SITE_ALG3 || variant == V_SITE_ALG3_XCD) {
         hipLaunchKernelGGL((stage_site_alg3_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
+    } else if (variant == V_SITE_LDS || variant == V_SITE_LDS_XCD) {
+        hipLaunchKernelGGL((stage_site_lds_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
     } else {
         hipLaunchKernelGGL((stage_link_kernel<R, NE>), dim3(tile_blocks), dim3(256), 0, s, b);
     }

@@ -388,8 +388,8 @@ __device__ __forceinline__ M3<R> lower_staple(const Links<R, NE> &W, const CfgDe
 // S += Z_{mu nu}(n-nu) U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu), accumulated in
 // place; the twist factor is folded into T = U_mu(n-nu) U_nu(n+mu-nu) as
 // z T^+ U = (conj(z) T)^+ U, so twisted and untwisted lanes run the same code.
-template <class R, int NE>
-__device__ __forceinline__ void acc_lower_staple(M3<R> &S, const Links<R, NE> &W,
+template <class R, class LK>
+__device__ __forceinline__ void acc_lower_staple(M3<R> &S, const LK &W,
                                                  const CfgDesc &c, const Geo &g, int mu, int nu) {
     const int imn = g.i + g.dn(nu);
     M3<R> T = mul_nn(W(mu, imn), W(nu, imn + g.up(mu)));

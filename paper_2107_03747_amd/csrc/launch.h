@@ -25,7 +25,10 @@ enum Variant {
     V_SITE_ALG_XCD = 7,
     V_SITE_ALG3 = 8,  // V_SITE_ALG capped at 168 registers (three waves per SIMD)
     V_SITE_ALG3_XCD = 9,
-    V_COUNT = 10
+    V_SITE_LDS = 10,  // V_SITE_ALG reading links of the work-group's own 256 sites
+                      // from an LDS copy
+    V_SITE_LDS_XCD = 11,
+    V_COUNT = 12
 };
 inline bool variant_is_split(int v) { return v == V_SPLIT || v == V_SPLIT_XCD; }
 const char *variant_name(int v);

@@ -238,6 +238,28 @@ def test_variants_agree(storage):
         assert rel.max() <= tol, (v, rel)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32c12"])
+def test_lds_staged_variant_batch(storage):
+    """The LDS-staged site variants on a batch whose work-groups straddle two
+    configurations (the unstaged path), whose last tiles are ragged, whose
+    (n0, n1) planes do and do not divide the 256-site block, with several
+    twisted planes; every configuration against the oracle."""
+    names = tgf.variant_names()
+    dims_list = [(4, 4, 12, 12), (3, 5, 4, 7), (10, 10, 6, 6), (6, 6, 18, 18)]
+    twists = [tgf.PAPER_TWIST, (1, 0, 2, 1, 0, 2), (2, 1, 0, 0, 1, 0), tgf.PAPER_TWIST]
+    Us = [gen.near_identity(d, 0.35, seed=40 + k).numpy().copy() for k, d in enumerate(dims_list)]
+    refs = [oracle.flow(U.copy(), d, 0.02, 0.1, 0.05, twist=tw)
+            for U, d, tw in zip(Us, dims_list, twists)]
+    for name in ("site_lds", "site_lds_xcd"):
+        say(f"  variant {name}")
+        f = tgf.Flow(list(zip(dims_list, twists)), storage)
+        f.set_variant(names.index(name))
+        f.load_all([torch.from_numpy(U).cuda() for U in Us])
+        rows = f.flow(0.02, 0.1, 0.05)
+        for k, d in enumerate(dims_list):
+            compare(rows[:refs[k].shape[0], k], refs[k], storage, f"{name} {d}")
+
+
 def test_resume_is_bitwise():
     U = torch.from_numpy(gen.near_identity(D1, 0.3, seed=14).numpy().copy()).cuda()
     a = tgf.Flow([D1], "f64")
