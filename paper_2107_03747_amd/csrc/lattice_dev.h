@@ -60,6 +60,31 @@ __device__ __forceinline__ void st(gptr<v2<R>> plane, unsigned off, cx<R> z) {
     *(gptr<v2<R>>)((gptr<char>)plane + off) = v;
 }
 
+// Non-temporal (streaming) stores and loads for data that no other lane of
+// the same launch touches again: link and accumulator outputs, accumulator
+// inputs.  They keep the per-XCD L2 for the neighbour links that are re-read
+// (stage launch with LDS staging: FP32 12-real -3%, FP64 -6%).
+template <class T>
+__device__ __forceinline__ void st_stream(gptr<T> p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+template <class T>
+__device__ __forceinline__ T ld_stream(gptr<const T> p) {
+    return __builtin_nontemporal_load(p);
+}
+template <class R>
+__device__ __forceinline__ void st_nt(gptr<v2<R>> plane, unsigned off, cx<R> z) {
+    v2<R> v;
+    v.x = z.x;
+    v.y = z.y;
+    st_stream((gptr<v2<R>>)((gptr<char>)plane + off), v);
+}
+template <class R>
+__device__ __forceinline__ cx<R> ld_nt(gptr<const v2<R>> plane, unsigned off) {
+    const v2<R> v = ld_stream((gptr<const v2<R>>)((gptr<const char>)plane + off));
+    return {v.x, v.y};
+}
+
 // ---------------------------------------------------------------------------
 // geometry
 
@@ -221,29 +246,31 @@ __device__ __forceinline__ void store_link(gptr<v2<R>> p, int stride, int mu, in
         a.x = U.e[0][0].x; a.y = U.e[0][0].y; a.z = U.e[0][1].x; a.w = U.e[0][1].y;
         b.x = U.e[0][2].x; b.y = U.e[0][2].y; b.z = U.e[1][0].x; b.w = U.e[1][0].y;
         c.x = U.e[1][1].x; c.y = U.e[1][1].y; c.z = U.e[1][2].x; c.w = U.e[1][2].y;
-        *(gptr<R4>)(q + u) = a;
-        *(gptr<R4>)(q + pl + u) = b;
-        *(gptr<R4>)(q + 2 * pl + u) = c;
+        st_stream((gptr<R4>)(q + u), a);
+        st_stream((gptr<R4>)(q + pl + u), b);
+        st_stream((gptr<R4>)(q + 2 * pl + u), c);
         if constexpr (NE == 9) {
             R4 d;
             d.x = U.e[2][0].x; d.y = U.e[2][0].y; d.z = U.e[2][1].x; d.w = U.e[2][1].y;
-            *(gptr<R4>)(q + 3 * pl + u) = d;
-            st(p + (size_t)(mu * 9 + 8) * stride, lane_off<R>(i), U.e[2][2]);
+            st_stream((gptr<R4>)(q + 3 * pl + u), d);
+            const v2<R> e8 = {U.e[2][2].x, U.e[2][2].y};
+            st_stream((gptr<v2<R>>)((gptr<char>)(p + (size_t)(mu * 9 + 8) * stride) + lane_off<R>(i)),
+                      e8);
         }
         return;
     } else {
         gptr<v2<R>> q = p + (size_t)(mu * NE) * stride;
         const unsigned u = lane_off<R>(i);
-        st(q, u, U.e[0][0]);
-        st(q + (size_t)stride, u, U.e[0][1]);
-        st(q + (size_t)2 * stride, u, U.e[0][2]);
-        st(q + (size_t)3 * stride, u, U.e[1][0]);
-        st(q + (size_t)4 * stride, u, U.e[1][1]);
-        st(q + (size_t)5 * stride, u, U.e[1][2]);
+        st_nt(q, u, U.e[0][0]);
+        st_nt(q + (size_t)stride, u, U.e[0][1]);
+        st_nt(q + (size_t)2 * stride, u, U.e[0][2]);
+        st_nt(q + (size_t)3 * stride, u, U.e[1][0]);
+        st_nt(q + (size_t)4 * stride, u, U.e[1][1]);
+        st_nt(q + (size_t)5 * stride, u, U.e[1][2]);
         if constexpr (NE == 9) {
-            st(q + (size_t)6 * stride, u, U.e[2][0]);
-            st(q + (size_t)7 * stride, u, U.e[2][1]);
-            st(q + (size_t)8 * stride, u, U.e[2][2]);
+            st_nt(q + (size_t)6 * stride, u, U.e[2][0]);
+            st_nt(q + (size_t)7 * stride, u, U.e[2][1]);
+            st_nt(q + (size_t)8 * stride, u, U.e[2][2]);
         }
     }
 }
@@ -252,15 +279,23 @@ __device__ __forceinline__ void store_link(gptr<v2<R>> p, int stride, int mu, in
 // [site] (the RK accumulator X, the plaquette algebra A).  FP32 pairs the
 // complex slots, [record][2][site][4 reals], so the record moves with two
 // 16-byte accesses; FP64 keeps four 16-byte planes.
-template <class R>
+template <class R, bool NT = true>
 __device__ __forceinline__ void ld_alg8(gptr<const v2<R>> base, int rec, int stride, int i,
                                         R out[8]) {
     if constexpr (sizeof(R) == 4) {
         typedef R R4 __attribute__((ext_vector_type(4)));
         gptr<const char> q = (gptr<const char>)(base + (size_t)(rec * 4) * stride);
         const unsigned u = (unsigned)i * 16u;
-        const R4 a = *(gptr<const R4>)(q + u);
-        const R4 b = *(gptr<const R4>)(q + (size_t)stride * 16u + u);
+        gptr<const R4> pa = (gptr<const R4>)(q + u);
+        gptr<const R4> pb = (gptr<const R4>)(q + (size_t)stride * 16u + u);
+        R4 a, b;
+        if constexpr (NT) {
+            a = ld_stream(pa);
+            b = ld_stream(pb);
+        } else {
+            a = *pa;
+            b = *pb;
+        }
         out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
         out[4] = b.x; out[5] = b.y; out[6] = b.z; out[7] = b.w;
     } else {
@@ -268,7 +303,7 @@ __device__ __forceinline__ void ld_alg8(gptr<const v2<R>> base, int rec, int str
         const unsigned u = lane_off<R>(i);
 #pragma unroll
         for (int t = 0; t < 4; t++) {
-            const cx<R> v = ld(q + (size_t)t * stride, u);
+            const cx<R> v = NT ? ld_nt(q + (size_t)t * stride, u) : ld(q + (size_t)t * stride, u);
             out[2 * t] = v.x;
             out[2 * t + 1] = v.y;
         }
@@ -285,13 +320,13 @@ __device__ __forceinline__ void st_alg8(gptr<v2<R>> base, int rec, int stride, i
         R4 a, b;
         a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
         b.x = v[4]; b.y = v[5]; b.z = v[6]; b.w = v[7];
-        *(gptr<R4>)(q + u) = a;
-        *(gptr<R4>)(q + (size_t)stride * 16u + u) = b;
+        st_stream((gptr<R4>)(q + u), a);
+        st_stream((gptr<R4>)(q + (size_t)stride * 16u + u), b);
     } else {
         gptr<v2<R>> q = base + (size_t)(rec * 4) * stride;
         const unsigned u = lane_off<R>(i);
 #pragma unroll
-        for (int t = 0; t < 4; t++) st(q + (size_t)t * stride, u, cx<R>{v[2 * t], v[2 * t + 1]});
+        for (int t = 0; t < 4; t++) st_nt(q + (size_t)t * stride, u, cx<R>{v[2 * t], v[2 * t + 1]});
     }
 }
 
