@@ -282,36 +282,46 @@ struct StagedLinks {
     int base;                 // first site of the block
     int staged;               // work-group uniform
     __device__ __forceinline__ M3<R> operator()(int mu, int j) const {
+        // the 16-byte units come from LDS or from global memory; the matrix
+        // (and the 12-real third row) is assembled once after the branch
         const unsigned k = (unsigned)(j - base);
+        constexpr bool kE8 = sizeof(R) == 4 && NE == 9;
+        U16 u[NU];
+        v2<R> e8;
         if (staged && __all(k < (unsigned)kBlock)) {
             const U16 *q = s16 + mu * NU * kBlock + k;
-            M3<R> U;
-            if constexpr (sizeof(R) == 4) {
-                const U16 a = q[0], b = q[kBlock], c = q[2 * kBlock];
-                U.e[0][0] = {a.x, a.y};
-                U.e[0][1] = {a.z, a.w};
-                U.e[0][2] = {b.x, b.y};
-                U.e[1][0] = {b.z, b.w};
-                U.e[1][1] = {c.x, c.y};
-                U.e[1][2] = {c.z, c.w};
-                if constexpr (NE == 9) {
-                    const U16 d = q[3 * kBlock];
-                    U.e[2][0] = {d.x, d.y};
-                    U.e[2][1] = {d.z, d.w};
-                    const v2<R> z = s8[mu * kBlock + k];
-                    U.e[2][2] = {z.x, z.y};
-                }
-            } else {
 #pragma unroll
-                for (int e = 0; e < NE; e++) {
-                    const U16 v = q[e * kBlock];
-                    U.e[e / 3][e % 3] = {v.x, v.y};
-                }
-            }
-            if constexpr (NE == 6) rebuild_row2(U);
-            return U;
+            for (int e = 0; e < NU; e++) u[e] = q[e * kBlock];
+            if constexpr (kE8) e8 = s8[mu * kBlock + k];
+        } else {
+            gptr<const char> q = (gptr<const char>)(gl.p + (size_t)(mu * NE) * gl.stride);
+            const size_t pl = (size_t)gl.stride * 16u;
+            const unsigned off = (unsigned)j * 16u;
+#pragma unroll
+            for (int e = 0; e < NU; e++) u[e] = *(gptr<const U16>)(q + e * pl + off);
+            if constexpr (kE8)
+                e8 = *(gptr<const v2<R>>)((gptr<const char>)(gl.p + (size_t)(mu * 9 + 8) * gl.stride) +
+                                          lane_off<R>(j));
         }
-        return gl(mu, j);
+        M3<R> U;
+        if constexpr (sizeof(R) == 4) {
+            U.e[0][0] = {u[0].x, u[0].y};
+            U.e[0][1] = {u[0].z, u[0].w};
+            U.e[0][2] = {u[1].x, u[1].y};
+            U.e[1][0] = {u[1].z, u[1].w};
+            U.e[1][1] = {u[2].x, u[2].y};
+            U.e[1][2] = {u[2].z, u[2].w};
+            if constexpr (NE == 9) {
+                U.e[2][0] = {u[3].x, u[3].y};
+                U.e[2][1] = {u[3].z, u[3].w};
+                U.e[2][2] = {e8.x, e8.y};
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < NE; e++) U.e[e / 3][e % 3] = {u[e].x, u[e].y};
+        }
+        if constexpr (NE == 6) rebuild_row2(U);
+        return U;
     }
 };
 
