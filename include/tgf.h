@@ -200,7 +200,8 @@ tgf_status tgf_unitarity(tgf_ctx *c, int32_t cfg, double *out);
 tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path);
 
 /* Select a stage-kernel variant by index (0 .. tgf_variant_count()-1), or
- * -1 for the built-in default. */
+ * -1 for the built-in default ("site_lds_xcd", the LDS-staged site kernel;
+ * general SU(N) contexts: variant 0). */
 tgf_status tgf_set_variant(tgf_ctx *c, int32_t variant);
 int32_t tgf_get_variant(tgf_ctx *c);
 int32_t tgf_variant_count(void);

@@ -186,7 +186,7 @@ struct tgf_ctx {
     int effective_variant() const {
         if (general) return variant >= 0 ? variant : 0;
         if (variant >= 0) return variant;
-        return st == TGF_F64_FULL ? V_LINK : V_SITE;
+        return V_SITE_LDS_XCD;   // the fastest measured for all three storages
     }
 };
 
