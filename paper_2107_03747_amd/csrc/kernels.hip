@@ -43,7 +43,7 @@ __device__ __forceinline__ void update_link_z(const LK &W, gptr<v2<R>> Wout,
     }
     if (stage < 2) st_alg8<R>(X, mu, stride, i, Z.a);
     M3<R> E = su3_exp<R, NE == 9 ? 3 : 2>(Z);
-    M3<R> U = W(mu, i);
+    M3<R> U = W.own(mu, i);
     M3<R> N;
     if constexpr (NE == 9) {
         N = mul_nn(E, U);
@@ -169,7 +169,7 @@ __device__ __forceinline__ void site_alg_update(const LK &W, gptr<v2<R>> Wout,
             // times a cube root of unity: two rows, projected like the upper
             // plaquettes
             const int imn = g.i + g.dn(nu);
-            R2<R> P = r2_of(W(MU, g.i));
+            R2<R> P = r2_of(W.own(MU, g.i));
             P = r2_mul_nd(P, W(nu, imn + g.up(MU)));
             P = r2_mul_nd(P, W(MU, imn));
             P = r2_mul_nn(P, W(nu, imn));
@@ -192,7 +192,7 @@ __device__ __forceinline__ void site_alg_update(const LK &W, gptr<v2<R>> Wout,
             if (nu == MU) continue;
             acc_lower_staple(S, W, c, g, MU, nu);
         }
-        const Alg<R> lo = proj_ah(mul_nn(W(MU, g.i), S), R(1));
+        const Alg<R> lo = proj_ah(mul_nn(W.own(MU, g.i), S), R(1));
 #pragma unroll
         for (int k = 0; k < 8; k++) Z.a[k] = -beps * (f.a[k] + lo.a[k]);
     }
@@ -217,10 +217,10 @@ __device__ __forceinline__ void site_alg_work(const LK &W, gptr<v2<R>> Wout, gpt
         for (int nu = mu + 1; nu < 4; nu++, p++) {
             // rows 0,1 of U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+, times Z^*; a
             // cube root of unity keeps the third row conj(row0 x row1)
-            R2<R> P = r2_of(W(mu, i));
+            R2<R> P = r2_of(W.own(mu, i));
             P = r2_mul_nn(P, W(nu, i + g.up(mu)));
             P = r2_mul_nd(P, W(mu, i + g.up(nu)));
-            P = r2_mul_nd(P, W(nu, i));
+            P = r2_mul_nd(P, W.own(nu, i));
             const int k = c.tw[p];
             if (k && g.n(mu) == 0 && g.n(nu) == 0) r2_scale(P, cconj(omega_pow<R>(k)));
             R A8[8];
@@ -281,14 +281,21 @@ struct StagedLinks {
     const v2<R> *s8;          // [mu][kBlock], FP32 full storage entry 8
     int base;                 // first site of the block
     int staged;               // work-group uniform
+    // a link of this lane's own site: in LDS whenever the block is staged
+    __device__ __forceinline__ M3<R> own(int mu, int i) const {
+        return fetch(mu, i, staged != 0);
+    }
     __device__ __forceinline__ M3<R> operator()(int mu, int j) const {
+        return fetch(mu, j, staged && __all((unsigned)(j - base) < (unsigned)kBlock));
+    }
+    __device__ __forceinline__ M3<R> fetch(int mu, int j, bool from_lds) const {
         // the 16-byte units come from LDS or from global memory; the matrix
         // (and the 12-real third row) is assembled once after the branch
         const unsigned k = (unsigned)(j - base);
         constexpr bool kE8 = sizeof(R) == 4 && NE == 9;
         U16 u[NU];
         v2<R> e8;
-        if (staged && __all(k < (unsigned)kBlock)) {
+        if (from_lds) {
             const U16 *q = s16 + mu * NU * kBlock + k;
 #pragma unroll
             for (int e = 0; e < NU; e++) u[e] = q[e * kBlock];

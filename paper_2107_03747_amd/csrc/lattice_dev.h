@@ -186,6 +186,7 @@ template <class R, int NE>
 struct Links {
     gptr<const v2<R>> p;
     int stride;
+    __device__ __forceinline__ M3<R> own(int mu, int i) const { return (*this)(mu, i); }
     __device__ __forceinline__ M3<R> operator()(int mu, int i) const {
         M3<R> U;
         if constexpr (sizeof(R) == 4) {
