@@ -179,17 +179,50 @@ __device__ __forceinline__ int find_cfg(const int *__restrict__ tile_start, int 
     return lo;
 }
 
+// A wave-uniform pointer taken through readfirstlane: the result is known to
+// be uniform (an SGPR pair) and opaque to re-association, so that
+// `sgpr_base(uniform) + lane offset` stays a global access with an SGPR base
+// and a 32-bit VGPR offset instead of 64-bit per-lane pointer arithmetic.
+// The argument must be the same in every active lane.
+template <class T>
+__device__ __forceinline__ gptr<T> sgpr_base(gptr<T> p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (gptr<T>)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+// A per-lane 32-bit offset re-materialised where it is used, so that the
+// instruction selector sees `SGPR base + zero-extended 32-bit offset` in the
+// same block as the access (a copy hoisted into another block arrives as a
+// 64-bit value and forces 64-bit address arithmetic).
+__device__ __forceinline__ unsigned lane_here(unsigned off) {
+    asm volatile("" : "+v"(off));
+    return off;
+}
+
 // ---------------------------------------------------------------------------
 // link storage: [mu][entry][stride] complex
+//
+// PIN (FP64): every entry plane's base goes through sgpr_base and the lane
+// offset through lane_here, so every access uses SGPR-base addressing.  The
+// Monte Carlo kernel uses it (+6% link updates/s from fewer 64-bit address
+// operations); the flow kernels measured equal or up to 2.5% slower with it
+// and keep the plain form.
 
-template <class R, int NE>
+template <class R, int NE, bool PIN = false>
 struct Links {
     gptr<const v2<R>> p;
     int stride;
     __device__ __forceinline__ M3<R> own(int mu, int i) const { return (*this)(mu, i); }
     __device__ __forceinline__ M3<R> operator()(int mu, int i) const {
         M3<R> U;
-        if constexpr (sizeof(R) == 4) {
+        if constexpr (PIN && sizeof(R) == 8) {
+            gptr<const v2<R>> q = p + (size_t)(mu * NE) * stride;
+            const unsigned u = lane_here(lane_off<R>(i));
+#pragma unroll
+            for (int e = 0; e < NE; e++) U.e[e / 3][e % 3] = ld(sgpr_base(q + (size_t)e * stride), u);
+            if constexpr (NE == 6) rebuild_row2(U);
+        } else if constexpr (sizeof(R) == 4) {
             // entry pairs: three (12-real) or four 16-byte loads, and for the
             // full storage entry 8 alone (entry_index)
             typedef R R4 __attribute__((ext_vector_type(4)));
@@ -235,10 +268,16 @@ struct Links {
     }
 };
 
-template <class R, int NE>
+template <class R, int NE, bool PIN = false>
 __device__ __forceinline__ void store_link(gptr<v2<R>> p, int stride, int mu, int i,
                                            const M3<R> &U) {
-    if constexpr (sizeof(R) == 4) {
+    if constexpr (PIN && sizeof(R) == 8) {
+        gptr<v2<R>> q = p + (size_t)(mu * NE) * stride;
+        const unsigned u = lane_here(lane_off<R>(i));
+#pragma unroll
+        for (int e = 0; e < NE; e++) st_nt(sgpr_base(q + (size_t)e * stride), u, U.e[e / 3][e % 3]);
+        return;
+    } else if constexpr (sizeof(R) == 4) {
         typedef R R4 __attribute__((ext_vector_type(4)));
         gptr<char> q = (gptr<char>)(p + (size_t)(mu * NE) * stride);
         const unsigned u = (unsigned)i * 16u;
@@ -381,8 +420,8 @@ __device__ __forceinline__ void reunitarise(M3<R> &U) {
 
 // Upper plaquette P_{mu nu}(n) = U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+,
 // multiplied by its twist factor Z^*_{mu nu}(n).
-template <class R, int NE>
-__device__ __forceinline__ M3<R> upper_plaq(const Links<R, NE> &W, const CfgDesc &c,
+template <class R, int NE, bool PN>
+__device__ __forceinline__ M3<R> upper_plaq(const Links<R, NE, PN> &W, const CfgDesc &c,
                                             const Geo &g, int mu, int nu) {
     // P is in SU(3): rows 0,1 by two-row products, row 2 = conj(row0 x row1)
     R2<R> A = r2_of(W(mu, g.i));
@@ -396,8 +435,8 @@ __device__ __forceinline__ M3<R> upper_plaq(const Links<R, NE> &W, const CfgDesc
 }
 
 // Upper staple U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+ times Z^*_{mu nu}(n).
-template <class R, int NE>
-__device__ __forceinline__ M3<R> upper_staple(const Links<R, NE> &W, const CfgDesc &c,
+template <class R, int NE, bool PN>
+__device__ __forceinline__ M3<R> upper_staple(const Links<R, NE, PN> &W, const CfgDesc &c,
                                               const Geo &g, int mu, int nu) {
     M3<R> A = mul_nd(W(nu, g.i + g.up(mu)), W(mu, g.i + g.up(nu)));
     A = mul_nd(A, W(nu, g.i));
@@ -409,8 +448,8 @@ __device__ __forceinline__ M3<R> upper_staple(const Links<R, NE> &W, const CfgDe
 // Lower staple U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu) times Z_{mu nu}(n-nu):
 // the plaquette P_{mu nu}(n-nu) enters the action with Z^*, and it contains
 // U_mu(n)^+, so its contribution to Omega_mu(n) is the adjoint.
-template <class R, int NE>
-__device__ __forceinline__ M3<R> lower_staple(const Links<R, NE> &W, const CfgDesc &c,
+template <class R, int NE, bool PN>
+__device__ __forceinline__ M3<R> lower_staple(const Links<R, NE, PN> &W, const CfgDesc &c,
                                               const Geo &g, int mu, int nu) {
     int imn = g.i + g.dn(nu);
     M3<R> T = mul_nn(W(mu, imn), W(nu, imn + g.up(mu)));
