@@ -197,16 +197,34 @@ __device__ __forceinline__ unsigned row_off(int r, int j, int stride, int site) 
     return ((unsigned)(r * N + j) * (unsigned)stride + (unsigned)site) * 16u;
 }
 
+// SGPR plane base + 32-bit lane offset for every access (sgpr_base,
+// lane_here, no 64-bit per-lane address arithmetic) where it measured
+// faster: stage launch (4,4) -34%, (6,2) -8%, (7,1) -1.5%, (3,3) -1%; the
+// other (N, rows per lane) builds ran 1-24% slower with it.
+template <int N, int R>
+constexpr bool sun_pin() {
+    return (N == 4 && R == 4) || (N == 6 && R == 2) || (N == 7 && R == 1) || (N == 3 && R == 3);
+}
+
 template <int N, int R>
 __device__ __forceinline__ Blk<N, R> load_blk(gptr<const v2<double>> W, int stride, int mu,
                                               const Grp &g, int site) {
     gptr<const v2<double>> q = W + (size_t)(mu * N * N) * stride;
     Blk<N, R> o;
+    if constexpr (sun_pin<N, R>()) {
+        q = sgpr_base(q);
 #pragma unroll
-    for (int i = 0; i < R; i++)
+        for (int i = 0; i < R; i++)
 #pragma unroll
-        for (int j = 0; j < N; j++)
-            o.e[i][j] = ld(q, row_off<N>(row_index<N, R>(g, i), j, stride, site));
+            for (int j = 0; j < N; j++)
+                o.e[i][j] = ld(q, lane_here(row_off<N>(row_index<N, R>(g, i), j, stride, site)));
+    } else {
+#pragma unroll
+        for (int i = 0; i < R; i++)
+#pragma unroll
+            for (int j = 0; j < N; j++)
+                o.e[i][j] = ld(q, row_off<N>(row_index<N, R>(g, i), j, stride, site));
+    }
     return o;
 }
 
@@ -214,10 +232,20 @@ template <int N, int R>
 __device__ __forceinline__ void store_blk(gptr<v2<double>> W, int stride, int mu, const Grp &g,
                                           int site, const Blk<N, R> &v) {
     gptr<v2<double>> q = W + (size_t)(mu * N * N) * stride;
+    if constexpr (sun_pin<N, R>()) {
+        q = sgpr_base(q);
 #pragma unroll
-    for (int i = 0; i < R; i++)
+        for (int i = 0; i < R; i++)
 #pragma unroll
-        for (int j = 0; j < N; j++) st(q, row_off<N>(row_index<N, R>(g, i), j, stride, site), v.e[i][j]);
+            for (int j = 0; j < N; j++)
+                st(q, lane_here(row_off<N>(row_index<N, R>(g, i), j, stride, site)), v.e[i][j]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < R; i++)
+#pragma unroll
+            for (int j = 0; j < N; j++)
+                st(q, row_off<N>(row_index<N, R>(g, i), j, stride, site), v.e[i][j]);
+    }
 }
 
 // twist exponent n_{mu nu} (mod N, antisymmetric) and Z = exp(2 pi i n / N)
