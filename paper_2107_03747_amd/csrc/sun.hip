@@ -199,11 +199,11 @@ __device__ __forceinline__ unsigned row_off(int r, int j, int stride, int site) 
 
 // SGPR plane base + 32-bit lane offset for every access (sgpr_base,
 // lane_here, no 64-bit per-lane address arithmetic) where it measured
-// faster: stage launch (4,4) -34%, (6,2) -8%, (7,1) -1.5%, (3,3) -1%; the
-// other (N, rows per lane) builds ran 1-24% slower with it.
+// faster over a whole flow: (4,4) +31%, (6,2) +10%, (7,1) +3%; the other
+// (N, rows per lane) builds ran up to 24% slower with it.
 template <int N, int R>
 constexpr bool sun_pin() {
-    return (N == 4 && R == 4) || (N == 6 && R == 2) || (N == 7 && R == 1) || (N == 3 && R == 3);
+    return (N == 4 && R == 4) || (N == 6 && R == 2) || (N == 7 && R == 1);
 }
 
 template <int N, int R>
