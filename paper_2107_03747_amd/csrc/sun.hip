@@ -530,9 +530,18 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
-// work-group = one tile; wave w measures the tile's sites 16 w .. 16 w + 15,
-// G at a time; the per-tile sums go to partials[tile][0], slots 1, 2 are zero
-// (the layout of the SU(3) measurement, so the same reduction finishes it)
+// work-group = one tile of WPB waves; wave w measures the tile's sites
+// SPW w .. SPW w + SPW - 1, G at a time (G = 64 / (N/R) sites fill a wave, so
+// one wave per tile when a lane holds a whole link, two when it holds half);
+// the per-tile sums go to partials[tile][0], slots 1, 2 are zero (the layout
+// of the SU(3) measurement, so the same reduction finishes it)
+template <int N, int R>
+struct MeasShape {
+    static constexpr int G = 64 / (N / R);
+    static constexpr int WPB = G >= 64 ? 1 : (G >= 32 ? 2 : 4);
+    static constexpr int SPW = 64 / WPB;
+};
+
 template <int N, int R>
 __global__ __launch_bounds__(256) void sun_measure_kernel(const CfgDesc *__restrict__ cfgs,
                                                           const int *__restrict__ tile_start,
@@ -547,15 +556,15 @@ __global__ __launch_bounds__(256) void sun_measure_kernel(const CfgDesc *__restr
     const CfgDesc c = cfgs[ci];
     const int sel = buf_sel < 0 ? c.cur : ((c.cur + buf_sel) & 1);
     gptr<const v2<double>> W = as_global<double>((const void *)(sel ? c.W[1] : c.W[0]));
-    constexpr int L = N / R, G = 64 / L;
+    constexpr int L = N / R, G = MeasShape<N, R>::G, SPW = MeasShape<N, R>::SPW;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane / L;
     const Grp gr{g * L, lane - g * L};
-    const int first = (tile - tile_start[ci]) * kTile + 16 * w;
+    const int first = (tile - tile_start[ci]) * kTile + SPW * w;
     double v[4] = {0, 0, 0, 0};
-    for (int s0 = 0; s0 < 16; s0 += G) {
+    for (int s0 = 0; s0 < SPW; s0 += G) {
         const int site = first + s0 + g;
-        if (g >= G || s0 + g >= 16 || site >= c.V) continue;
+        if (g >= G || s0 + g >= SPW || site >= c.V) continue;
         measure_site_n<N, R>(W, c, make_geo(c, site), gr, v);
     }
     __shared__ double red[4][4];
@@ -568,7 +577,11 @@ __global__ __launch_bounds__(256) void sun_measure_kernel(const CfgDesc *__restr
     if (threadIdx.x < 12) {
         const int slot = threadIdx.x >> 2, k = threadIdx.x & 3;
         double *o = partials + ((size_t)tile * 3 + slot) * 4 + k;
-        *o = slot ? 0.0 : (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+        constexpr int WPB = MeasShape<N, R>::WPB;
+        const double t = WPB == 1 ? red[0][k]
+                       : WPB == 2 ? red[0][k] + red[1][k]
+                                  : (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+        *o = slot ? 0.0 : t;
     }
 }
 
@@ -716,7 +729,8 @@ static hipError_t stage_nr(hipStream_t s, const SunStageArgs &a) {
 template <int N, int R>
 static hipError_t measure_nr(hipStream_t s, const CfgDesc *cfgs, const int *tile_start, int n_cfg,
                              int n_tiles, const MeasSlot *slots, double *partials, int buf_sel) {
-    hipLaunchKernelGGL((sun_measure_kernel<N, R>), dim3(n_tiles), dim3(256), 0, s, cfgs,
+    hipLaunchKernelGGL((sun_measure_kernel<N, R>), dim3(n_tiles), dim3(64 * MeasShape<N, R>::WPB), 0,
+                       s, cfgs,
                        tile_start, n_cfg, n_tiles, slots, partials, buf_sel);
     return hipGetLastError();
 }
