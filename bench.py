@@ -94,7 +94,7 @@ def flops_per_site_stage(storage, variant, part=1):
     """Real FP operations per site for one RK stage, by kernel."""
     c12 = storage == "f32c12"
     upd = R2 if c12 else MM
-    if variant.startswith(("site_alg", "site_lds")):
+    if variant.startswith(("site_alg", "site_lds", "site_plq")):
         if storage == "f64":
             # six two-row plaquettes projected to su(3) (r2_proj_ah ~55, +-accumulate 16),
             # twelve lower staples (a product and an accumulated product, 2 MM + 18),
@@ -523,6 +523,8 @@ def main():
         kname = "stage_site_alg3_kernel"
     elif variant.startswith("site_lds"):
         kname = "stage_site_lds_kernel"
+    elif variant.startswith("site_plq"):
+        kname = "stage_site_plq_kernel"
     elif variant.startswith("site_alg"):
         # FP32 runs the two-waves-per-SIMD build of the same kernel
         kname = "stage_site_alg_kernel" if args.storage == "f64" else "stage_site_alg2_kernel"

@@ -399,6 +399,150 @@ void stage_site_lds_kernel(StageArgs a) {
     site_lds_body<R, NE>(a);
 }
 
+// Lower staple terms of link MU (from the block's plaquettes in LDS where the
+// whole wave finds them there, else formed directly) and the RK update.
+template <class R, int NE, int MU, class U16>
+__device__ __forceinline__ void plq_update(const Links<R, NE> &W, gptr<v2<R>> Wout, gptr<v2<R>> X,
+                                           const CfgDesc &c, const Geo &g, const Alg<R> &f,
+                                           R beps, R ac, const StageArgs &a, const U16 *sA,
+                                           int base, int staged) {
+    constexpr int NA = 8 * (int)sizeof(R) / 16;
+    Alg<R> Z = f;
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == MU) continue;
+        const int imn = g.i + g.dn(nu);
+        const unsigned k = (unsigned)(imn - base);
+        R A8[8];
+        if (staged && __all(k < (unsigned)kBlock)) {
+            const int p = MU < nu ? (MU == 0 ? nu - 1 : (MU == 1 ? nu + 1 : 5))
+                                      : (nu == 0 ? MU - 1 : (nu == 1 ? MU + 1 : 5));
+            const U16 *q = sA + p * NA * kBlock + k;
+            R am[8];
+#pragma unroll
+            for (int u = 0; u < NA; u++) {
+                const U16 v = q[u * kBlock];
+                if constexpr (sizeof(R) == 4) {
+                    am[4 * u] = v.x; am[4 * u + 1] = v.y; am[4 * u + 2] = v.z; am[4 * u + 3] = v.w;
+                } else {
+                    am[2 * u] = v.x; am[2 * u + 1] = v.y;
+                }
+            }
+            conj_alg(W(nu, imn), am, A8);
+            const R sg = MU < nu ? R(-1) : R(1);
+#pragma unroll
+            for (int t = 0; t < 8; t++) A8[t] *= sg;
+        } else {
+            R2<R> P = r2_of(W(MU, g.i));
+            P = r2_mul_nd(P, W(nu, imn + g.up(MU)));
+            P = r2_mul_nd(P, W(MU, imn));
+            P = r2_mul_nn(P, W(nu, imn));
+            const int kt = twist_exp(c, MU, nu);
+            if (kt && g.n(MU) == 0 && g.back(nu) == 0) r2_scale(P, omega_pow<R>(kt));
+            r2_proj_ah(P, R(1), A8);
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t++) Z.a[t] += A8[t];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; t++) Z.a[t] *= -beps;
+    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, a.reunit);
+}
+
+// ---------------------------------------------------------------------------
+// Plaquette-sharing site variant.  A work-group owns 256 consecutive sites of
+// one configuration.  Each lane first forms its six upper plaquettes
+// A_{mu nu}(n) = P_ah(Z^* P_{mu nu}(n)) (two-row products, as site_alg) and
+// keeps them in LDS ([plane][16-byte unit][site]); after a barrier, a lower
+// staple term of link mu in plane nu whose plaquette P_{mu nu}(n-nu) belongs
+// to a site of the block (all active lanes of the wave) is taken from there:
+//   P_ah(U_mu(n) x lower staple) = -/+ U_nu(n-nu)^+ A_{min max}(n-nu) U_nu(n-nu)
+// (- for mu < nu, + for mu > nu; P_ah is linear and commutes with the
+// conjugation), one link load and one conjugation instead of three links and
+// three two-row products.  Other lower terms are formed directly.  Work-groups
+// whose tiles span two configurations skip the LDS (no barrier).
+
+template <class R, int NE>
+__device__ __forceinline__ void site_plq_body(const StageArgs &a) {
+    typedef R U16 __attribute__((ext_vector_type(16 / sizeof(R))));
+    constexpr int NA = 8 * (int)sizeof(R) / 16;      // 16-byte units per su(3) element
+    __shared__ U16 sA[6 * NA * kBlock];
+
+    const int nb = (a.n_tiles + 3) >> 2;
+    const int b = remap_block(blockIdx.x, nb, a.xcd);
+    if (b >= nb) return;                                   // whole work-group
+    const int t0 = b * 4;
+    const int tile = t0 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ci0 = find_cfg(a.tile_start, a.n_act, t0);
+    const int staged = t0 + 3 < a.n_tiles && find_cfg(a.tile_start, a.n_act, t0 + 3) == ci0;
+    if (!staged && tile >= a.n_tiles) return;
+    const int ci = staged ? ci0 : find_cfg(a.tile_start, a.n_act, tile);
+    const CfgDesc c = a.cfgs[ci];
+    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
+    const int base = (t0 - a.tile_start[ci]) * kTile;
+
+    const int in = (c.cur + 3 * a.step + a.stage) & 1;
+    const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
+    const Geo g = make_geo(c, i < c.V ? i : 0);
+
+    Alg<R> f[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++)
+#pragma unroll
+        for (int k = 0; k < 8; k++) f[mu].a[k] = R(0);
+    if (i < c.V) {
+#pragma unroll
+        for (int mu = 0, p = 0; mu < 4; mu++)
+#pragma unroll
+            for (int nu = mu + 1; nu < 4; nu++, p++) {
+                R2<R> P = r2_of(W(mu, i));
+                P = r2_mul_nn(P, W(nu, i + g.up(mu)));
+                P = r2_mul_nd(P, W(mu, i + g.up(nu)));
+                P = r2_mul_nd(P, W(nu, i));
+                const int k = c.tw[p];
+                if (k && g.n(mu) == 0 && g.n(nu) == 0) r2_scale(P, cconj(omega_pow<R>(k)));
+                R A8[8];
+                r2_proj_ah(P, R(1), A8);
+#pragma unroll
+                for (int t = 0; t < 8; t++) {
+                    f[mu].a[t] += A8[t];
+                    f[nu].a[t] -= A8[t];
+                }
+                if (staged) {
+                    U16 *o = sA + p * NA * kBlock + threadIdx.x;
+#pragma unroll
+                    for (int u = 0; u < NA; u++) {
+                        U16 v;
+                        if constexpr (sizeof(R) == 4) {
+                            v.x = A8[4 * u]; v.y = A8[4 * u + 1]; v.z = A8[4 * u + 2]; v.w = A8[4 * u + 3];
+                        } else {
+                            v.x = A8[2 * u]; v.y = A8[2 * u + 1];
+                        }
+                        o[u * kBlock] = v;
+                    }
+                }
+            }
+    }
+    if (staged) __syncthreads();
+    if (i >= c.V) return;
+
+    gptr<v2<R>> Wout = as_global<R>(in ? c.W[0] : c.W[1]);
+    gptr<v2<R>> X = as_global<R>(c.X);
+    const double eps = a.step < c.n_full ? a.eps : c.eps_last;
+    const R beps = (R)(kRkB[a.stage] * eps);
+    const R ac = (R)kRkA[a.stage];
+    plq_update<R, NE, 0>(W, Wout, X, c, g, f[0], beps, ac, a, sA, base, staged);
+    plq_update<R, NE, 1>(W, Wout, X, c, g, f[1], beps, ac, a, sA, base, staged);
+    plq_update<R, NE, 2>(W, Wout, X, c, g, f[2], beps, ac, a, sA, base, staged);
+    plq_update<R, NE, 3>(W, Wout, X, c, g, f[3], beps, ac, a, sA, base, staged);
+}
+
+template <class R, int NE>
+__global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : (NE == 6 ? 3 : 2))
+void stage_site_plq_kernel(StageArgs a) {
+    site_plq_body<R, NE>(a);
+}
+
 // Register budgets: FP64 keeps the whole working set in 512 registers (one
 // wave per SIMD); FP32 is capped at 256 (two waves per SIMD).
 template <class R, int NE>
@@ -992,6 +1136,8 @@ const char *variant_name(int v) {
         case V_SITE_ALG3_XCD: return "site_alg3_xcd";
         case V_SITE_LDS: return "site_lds";
         case V_SITE_LDS_XCD: return "site_lds_xcd";
+        case V_SITE_PLQ: return "site_plq";
+        case V_SITE_PLQ_XCD: return "site_plq_xcd";
         default: return "?";
     }
 }
@@ -1000,7 +1146,7 @@ template <class R, int NE>
 static hipError_t launch_stage_t(int variant, int part, hipStream_t s, const StageArgs &a) {
     const bool xcd = variant == V_SITE_XCD || variant == V_LINK_XCD || variant == V_SPLIT_XCD ||
                      variant == V_SITE_ALG_XCD || variant == V_SITE_ALG3_XCD ||
-                     variant == V_SITE_LDS_XCD;
+                     variant == V_SITE_LDS_XCD || variant == V_SITE_PLQ_XCD;
     StageArgs b = a;
     b.xcd = xcd ? 1 : 0;
     const int site_blocks = xcd ? ((a.n_tiles + 3) / 4 + 7) / 8 * 8 : (a.n_tiles + 3) / 4;
@@ -1024,6 +1170,8 @@ static hipError_t launch_stage_t(int variant, int part, hipStream_t s, const Sta
         hipLaunchKernelGGL((stage_site_alg3_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
     } else if (variant == V_SITE_LDS || variant == V_SITE_LDS_XCD) {
         hipLaunchKernelGGL((stage_site_lds_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
+    } else if (variant == V_SITE_PLQ || variant == V_SITE_PLQ_XCD) {
+        hipLaunchKernelGGL((stage_site_plq_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
     } else {
         hipLaunchKernelGGL((stage_link_kernel<R, NE>), dim3(tile_blocks), dim3(256), 0, s, b);
     }

@@ -28,7 +28,10 @@ enum Variant {
     V_SITE_LDS = 10,  // V_SITE_ALG reading links of the work-group's own 256 sites
                       // from an LDS copy
     V_SITE_LDS_XCD = 11,
-    V_COUNT = 12
+    V_SITE_PLQ = 12,  // V_SITE_ALG with the block's upper plaquettes kept in LDS and
+                      // reused, conjugated, as in-block lower staple terms
+    V_SITE_PLQ_XCD = 13,
+    V_COUNT = 14
 };
 inline bool variant_is_split(int v) { return v == V_SPLIT || v == V_SPLIT_XCD; }
 const char *variant_name(int v);

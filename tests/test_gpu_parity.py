@@ -240,7 +240,8 @@ def test_variants_agree(storage):
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f32c12"])
 def test_lds_staged_variant_batch(storage):
-    """The LDS-staged site variants on a batch whose work-groups straddle two
+    """The LDS-staged site variants (staged links; staged plaquettes reused as
+    lower staple terms) on a batch whose work-groups straddle two
     configurations (the unstaged path), whose last tiles are ragged, whose
     (n0, n1) planes do and do not divide the 256-site block, with several
     twisted planes; every configuration against the oracle."""
@@ -250,7 +251,7 @@ def test_lds_staged_variant_batch(storage):
     Us = [gen.near_identity(d, 0.35, seed=40 + k).numpy().copy() for k, d in enumerate(dims_list)]
     refs = [oracle.flow(U.copy(), d, 0.02, 0.1, 0.05, twist=tw)
             for U, d, tw in zip(Us, dims_list, twists)]
-    for name in ("site_lds", "site_lds_xcd"):
+    for name in ("site_lds", "site_lds_xcd", "site_plq", "site_plq_xcd"):
         say(f"  variant {name}")
         f = tgf.Flow(list(zip(dims_list, twists)), storage)
         f.set_variant(names.index(name))
