@@ -195,6 +195,9 @@ tgf_status tgf_unitarity(tgf_ctx *c, int32_t cfg, double *out);
 
 /* Time the candidate stage-kernel variants on the loaded links (a few stages
  * each, links restored afterwards) and keep the fastest for this context.
+ * Candidates are the variants whose result for a configuration does not
+ * depend on the other configurations of the batch (all but "site_plq" and
+ * "site_plq_xcd", which tgf_set_variant still selects).
  * cache_path (may be NULL): a text file of "key variant" lines read before
  * and appended after tuning.  Synchronises. */
 tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path);

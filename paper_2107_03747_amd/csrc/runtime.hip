@@ -976,6 +976,11 @@ tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path) {
         return err;
     };
     for (int v = 0; v < c->variant_count(); v++) {
+        // the plaquette-sharing variants take a lower staple term from LDS or
+        // form it directly depending on which configurations share a
+        // work-group, so a configuration's result would depend on the batch
+        // around it; they are selected only explicitly (tgf_set_variant)
+        if (!c->general && (v == V_SITE_PLQ || v == V_SITE_PLQ_XCD)) continue;
         hipError_t err = stage0(v);
         if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
         for (int r = 0; r < reps && err == hipSuccess; r++) err = stage0(v);
