@@ -727,7 +727,6 @@ __global__ __launch_bounds__(256) void plaq_alg_kernel(StageArgs a) {
     const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
     gptr<v2<R>> Ap = as_global<R>(c.A);
     const Geo g = make_geo(c, i);
-    const unsigned u = lane_off<R>(i);
 #pragma unroll
     for (int mu = 0, p = 0; mu < 4; mu++)
 #pragma unroll
