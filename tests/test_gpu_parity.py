@@ -261,6 +261,23 @@ def test_lds_staged_variant_batch(storage):
             compare(rows[:refs[k].shape[0], k], refs[k], storage, f"{name} {d}")
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32c12"])
+def test_all_planes_twisted_plane_tiles(storage):
+    """8x8 (n0, n1) planes fill a 64-site tile exactly, so the 12-real site
+    kernel takes its lower staple terms in directions 0 and 1 from the
+    plaquettes of neighbouring lanes; every plane twisted (n_{mu nu} = 1 or
+    2), so each such term carries a twist factor of its own plane.  Default
+    variant and both LDS block orders, against the oracle."""
+    dims = (8, 8, 4, 6)
+    twist = (1, 2, 1, 2, 1, 2)
+    U = gen.near_identity(dims, 0.35, seed=77).numpy().copy()
+    ref = oracle.flow(U.copy(), dims, 0.02, 0.1, 0.05, twist=twist)
+    names = tgf.variant_names()
+    for v in (None, names.index("site_lds"), names.index("site_lds_xcd")):
+        rows, _ = gpu_flow([dims], storage, [U], 0.02, 0.1, 0.05, variant=v, twist=twist)
+        compare(rows[:, 0], ref, storage, f"all planes twisted, variant {v}")
+
+
 def test_resume_is_bitwise():
     U = torch.from_numpy(gen.near_identity(D1, 0.3, seed=14).numpy().copy()).cuda()
     a = tgf.Flow([D1], "f64")
