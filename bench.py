@@ -73,7 +73,8 @@ def n_steps(t_end, t0=0.0):
     return n + (1 if t_end - (t0 + n * EPS) > 1e-12 else 0)
 
 
-# Algorithmic work per site per RK3 step (3 stages) -- see the design doc.
+# Algorithmic work per site per RK3 step (3 stages): every link and accumulator
+# element an RK stage touches, once, with ping-pong link buffers.
 def bytes_per_site_step(storage, variant="site"):
     ne, cb = (6, 8) if storage == "f32c12" else ((9, 8) if storage == "f32" else (9, 16))
     links = 3 * 2 * 4 * ne * cb           # read + write every stage
