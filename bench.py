@@ -79,10 +79,7 @@ def bytes_per_site_step(storage, variant="site"):
     ne, cb = (6, 8) if storage == "f32c12" else ((9, 8) if storage == "f32" else (9, 16))
     links = 3 * 2 * 4 * ne * cb           # read + write every stage
     x = (1 + 2 + 1) * 4 * 4 * cb          # X: write, read+write, read
-    extra = 0
-    if variant.startswith("split"):       # A written + read, links read by both parts
-        extra = 3 * (2 * 6 * 4 * cb + 4 * ne * cb)
-    return links + x + extra
+    return links + x
 
 
 MM = 198.0            # 3x3 complex product: 27 complex multiplies + 18 complex adds
@@ -91,7 +88,7 @@ REBUILD = 42.0        # row 2 = conj(row0 x row1): 6 complex multiplies + 3 subt
 EXP, XUPD = 300.0, 56.0
 
 
-def flops_per_site_stage(storage, variant, part=1):
+def flops_per_site_stage(storage, variant):
     """Real FP operations per site for one RK stage, by kernel."""
     c12 = storage == "f32c12"
     upd = R2 if c12 else MM
@@ -111,17 +108,12 @@ def flops_per_site_stage(storage, variant, part=1):
                 + (REBUILD * 51 if c12 else 0))
     if variant.startswith("site"):
         return 46 * MM + 4 * (EXP + upd + XUPD) + (REBUILD * 44 if c12 else 0)
-    if variant.startswith("link"):
-        return 4 * (13 * MM + EXP + upd + XUPD) + (REBUILD * 4 * 19 if c12 else 0)
-    if part == 0:     # six plaquettes as two-row products + 2.5 rebuilt entries + P_ah
-        return 6 * (3 * R2 + 35 + 16) + (REBUILD * 16 if c12 else 0)
-    # part 1: three conjugations U^+ A U (258) per link + exponential + update
-    return 4 * (3 * 258 + 24 + EXP + upd + XUPD) + (REBUILD * 16 if c12 else 0)
+    # one thread per link: six staples and U S per link
+    return 4 * (13 * MM + EXP + upd + XUPD) + (REBUILD * 4 * 19 if c12 else 0)
 
 
 def flops_per_site_step(storage, variant):
-    parts = (0, 1) if variant.startswith("split") else (1,)
-    return 3 * sum(flops_per_site_stage(storage, variant, p) for p in parts)
+    return 3 * flops_per_site_stage(storage, variant)
 
 
 def kernel_source_hash():
@@ -513,7 +505,7 @@ def main():
     stage_avg_ms = tm["stage_ms"] / n_launch
     bytes_per_launch = tm["stage_bytes"] / n_launch
     site_stages_per_launch = 3 * tm["stage_site_updates"] / n_launch
-    flops_per_launch = site_stages_per_launch * flops_per_site_stage(args.storage, variant, 1)
+    flops_per_launch = site_stages_per_launch * flops_per_site_stage(args.storage, variant)
     gbs = bytes_per_launch / (stage_avg_ms * 1e-3) / 1e9
     tflops = flops_per_launch / (stage_avg_ms * 1e-3) / 1e12
     hbm_frac = gbs / HBM_PEAK_GBS
@@ -530,8 +522,7 @@ def main():
         # FP32 runs the two-waves-per-SIMD build of the same kernel
         kname = "stage_site_alg_kernel" if args.storage == "f64" else "stage_site_alg2_kernel"
     else:
-        kname = {"site": "stage_site_kernel", "link": "stage_link_kernel",
-                 "split": "split_link_kernel"}[variant.split("_")[0]]
+        kname = {"site": "stage_site_kernel", "link": "stage_link_kernel"}[variant.split("_")[0]]
     targ = "double, 9" if args.storage == "f64" else ("float, 6" if args.storage == "f32c12"
                                                       else "float, 9")
     roofline = {
@@ -553,7 +544,6 @@ def main():
         "flops_per_launch": round(flops_per_launch),
         "bytes_per_site_step": bytes_per_site_step(args.storage, variant),
         "flops_per_site_step": round(flops_per_site_step(args.storage, variant)),
-        "aux_kernel_ms_per_flow": round(tm["aux_ms"], 3),
         "measure_ms_per_flow": round(tm["measure_ms"], 3),
     }
     whole_gbs = site_updates * bytes_per_site_step(args.storage, variant) / dt / 1e9

@@ -93,7 +93,10 @@ typedef struct {
     double eps;            /* step size, > 0 */
     const double *t_end;   /* [n_cfg] host array, t_end[c] >= current t of cfg c */
     double meas_dt;        /* measurement grid spacing; 0 = only at t_end */
-    int32_t reunit_every;  /* FP32 storages: reunitarise in FP64 every R steps (0 = never);
+    int32_t reunit_every;  /* FP32 storages: reunitarise in FP64 at the end of every R-th
+                              step of each configuration, steps counted from its last
+                              tgf_load_links* (or tgf_mc), so the schedule is the same
+                              however a flow is split into calls (0 = never);
                               ignored for TGF_F64_FULL */
     uint32_t flags;        /* TGF_NO_GRAPH | TGF_TIMING */
 } tgf_flow_params;
@@ -105,9 +108,6 @@ typedef struct {
     int64_t stage_launches;   /* number of those launches (one per stage) */
     double stage_bytes;       /* algorithmic HBM bytes of those launches */
     double stage_site_updates;/* site-stage updates / 3 (= site-updates) */
-    double aux_ms;            /* plaquette-algebra kernels of the split variants */
-    int64_t aux_launches;
-    double aux_bytes;         /* their algorithmic HBM bytes */
     double measure_ms;        /* measurement + reduction kernels */
     int64_t measure_launches;
 } tgf_timing;
@@ -172,6 +172,24 @@ tgf_status tgf_store_links(tgf_ctx *c, int32_t cfg, void *links_dev);
 
 /* Current flow time of cfg. */
 tgf_status tgf_get_time(tgf_ctx *c, int32_t cfg, double *t);
+
+/* Per-site densities of cfg at its current flow time (sec. 3.1, eq. gmunu and
+ * eq. qlatt), FP64, canonical site order (n0 fastest), V doubles each in
+ * device memory owned by the caller (either pointer may be NULL):
+ *   e_dev[n] = sum_{mu<nu} Tr G_{mu nu}(n)^2, so that E = (1/V) sum_n e(n);
+ *   q_dev[n] = (1/16 pi^2) Tr G G~ (n), so that Q = sum_n q(n).
+ * The clover G is computed in the context's precision (FP32 for the FP32
+ * storages) and each site's sum is converted to FP64.  TGF_E_STATE if cfg is
+ * not loaded.  Enqueued only; the caller synchronises the stream. */
+tgf_status tgf_densities(tgf_ctx *c, int32_t cfg, double *e_dev, double *q_dev);
+
+/* Where cfg's links are stored now: *offset = byte offset within the
+ * workspace, *bytes = size of that storage buffer (structure of arrays
+ * [mu][entry][site], FP32 entries paired; the layout is internal to the
+ * library).  For callers that checksum, snapshot or poison the stored field in
+ * place; the buffer alternates with every RK stage, so the answer holds until
+ * the next tgf_flow or tgf_load_links*.  TGF_E_STATE if cfg is not loaded. */
+tgf_status tgf_link_buffer(tgf_ctx *c, int32_t cfg, size_t *offset, size_t *bytes);
 
 /* Measure every loaded configuration at its current flow time:
  * out_host[n_cfg].  Synchronises. */

@@ -30,7 +30,8 @@
 namespace tgf {
 
 // RK stage tail for one link, from Z = B eps F in the 8-real form:
-// X = Z + A X_old; W_out = exp(X) W_in.
+// X = Z + A X_old; W_out = exp(X) W_in, formed as W_in + (exp(X) - 1) W_in so
+// that FP32 rounding has no preferred direction (su3_expm1).
 template <class R, int NE, class LK>
 __device__ __forceinline__ void update_link_z(const LK &W, gptr<v2<R>> Wout,
                                               gptr<v2<R>> X, int stride, int mu, int i,
@@ -42,22 +43,10 @@ __device__ __forceinline__ void update_link_z(const LK &W, gptr<v2<R>> Wout,
         for (int k = 0; k < 8; k++) Z.a[k] = fma(a, o[k], Z.a[k]);
     }
     if (stage < 2) st_alg8<R>(X, mu, stride, i, Z.a);
-    M3<R> E = su3_exp<R, NE == 9 ? 3 : 2>(Z);
-    M3<R> U = W.own(mu, i);
-    M3<R> N;
-    if constexpr (NE == 9) {
-        N = mul_nn(E, U);
-    } else {
-#pragma unroll
-        for (int r = 0; r < 2; r++)
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                cx<R> s = cmul(E.e[r][0], U.e[0][j]);
-                s = cmadd(s, E.e[r][1], U.e[1][j]);
-                s = cmadd(s, E.e[r][2], U.e[2][j]);
-                N.e[r][j] = s;
-            }
-    }
+    constexpr int ROWS = NE == 9 ? 3 : 2;
+    const M3<R> D = su3_expm1<R, ROWS>(Z);
+    const M3<R> U = W.own(mu, i);
+    M3<R> N = mul_add_expm1<R, ROWS>(D, U);
     if (reunit) reunitarise(N);
     store_link<R, NE>(Wout, stride, mu, i, N);
 }
@@ -82,9 +71,18 @@ struct StageArgs {
     int step;
     int stage;
     double eps;
-    int reunit;
+    int reunit_every;   // FP64 reunitarisation every this many steps (0 = never)
     int xcd;        // 1: remap blocks so each XCD owns a contiguous tile range
 };
+
+// Reunitarise at the end of this step of configuration c?  Steps are counted
+// from the load of the configuration (reunit_phase = steps done before this
+// flow call, modulo reunit_every), so the schedule does not depend on how a
+// caller splits a flow into calls.
+__device__ __forceinline__ int reunit_now(const StageArgs &a, const CfgDesc &c) {
+    return a.stage == 2 && a.reunit_every > 0 &&
+           (c.reunit_phase + a.step + 1) % a.reunit_every == 0;
+}
 
 // Lower staples of link MU summed, Omega_MU += U_MU(n) S, then the RK update
 // (MU is a template argument so that acc[] is never indexed at run time).
@@ -100,7 +98,7 @@ __device__ __forceinline__ void site_lower_update(const Links<R, NE> &W, gptr<v2
         acc_lower_staple(S, W, c, g, MU, nu);
     }
     m_acc_mul_nn(om, W(MU, g.i), S);
-    update_link<R, NE>(W, Wout, X, c.stride, MU, g.i, om, beps, ac, a.stage, a.reunit);
+    update_link<R, NE>(W, Wout, X, c.stride, MU, g.i, om, beps, ac, a.stage, reunit_now(a, c));
 }
 
 // One thread per site: the six upper plaquettes feed both of their links
@@ -196,7 +194,7 @@ __device__ __forceinline__ void site_alg_update(const LK &W, gptr<v2<R>> Wout,
 #pragma unroll
         for (int k = 0; k < 8; k++) Z.a[k] = -beps * (f.a[k] + lo.a[k]);
     }
-    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, a.reunit);
+    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, reunit_now(a, c));
 }
 
 // The force of the four links of site g.i from su(3) accumulators, then the
@@ -260,7 +258,7 @@ __device__ __forceinline__ void wave_update(const LK &W, gptr<v2<R>> Wout, gptr<
     }
 #pragma unroll
     for (int t = 0; t < 8; t++) Z.a[t] *= -beps;
-    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, a.reunit);
+    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, reunit_now(a, c));
 }
 
 // site_alg_work with in-wave plaquette reuse (FP32): a lane's lower staple
@@ -542,7 +540,7 @@ __device__ __forceinline__ void plq_update(const Links<R, NE> &W, gptr<v2<R>> Wo
     }
 #pragma unroll
     for (int t = 0; t < 8; t++) Z.a[t] *= -beps;
-    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, a.reunit);
+    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, reunit_now(a, c));
 }
 
 // ---------------------------------------------------------------------------
@@ -681,7 +679,7 @@ __device__ __forceinline__ void link_body(const StageArgs &a, const CfgDesc &c, 
         m_acc(S, lower_staple(W, c, g, MU, nu));
     }
     M3<R> Om = mul_nn(W(MU, i), S);
-    update_link<R, NE>(W, Wout, X, c.stride, MU, i, Om, beps, ac, a.stage, a.reunit);
+    update_link<R, NE>(W, Wout, X, c.stride, MU, i, Om, beps, ac, a.stage, reunit_now(a, c));
 }
 
 template <class R, int NE>
@@ -699,133 +697,6 @@ __global__ __launch_bounds__(256) void stage_link_kernel(StageArgs a) {
         case 1: link_body<R, NE, 1>(a, c, i); break;
         case 2: link_body<R, NE, 2>(a, c, i); break;
         default: link_body<R, NE, 3>(a, c, i); break;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// split stage: the force projection is linear and commutes with conjugation,
-//   P_ah(Omega_mu(n)) = sum_{nu != mu} [ A_{mu nu}(n) - U_nu(n-nu)^+ A_{mu nu}(n-nu) U_nu(n-nu) ],
-//   A_{mu nu}(n) = P_ah(Z^*_{mu nu}(n) P_{mu nu}(n)),  A_{nu mu} = -A_{mu nu},
-// because the lower staple term of Omega_mu(n) is the plaquette
-// Z^* P_{mu nu}(n-nu), adjoined and conjugated by U_nu(n-nu).  Part 0 writes
-// the six A_{mu nu}(n) of every site once per stage (each plaquette is built
-// once per lattice instead of up to four times); part 1 forms the force of
-// every link from three own and three neighbouring A and updates the link.
-
-template <class R, int NE>
-__global__ __launch_bounds__(256) void plaq_alg_kernel(StageArgs a) {
-    const int nb = (a.n_tiles + 3) >> 2;
-    const int b = remap_block(blockIdx.x, nb, a.xcd);
-    if (b >= nb) return;
-    const int tile = b * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (tile >= a.n_tiles) return;
-    const int ci = find_cfg(a.tile_start, a.n_act, tile);
-    const CfgDesc c = a.cfgs[ci];
-    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
-    if (i >= c.V) return;
-    const int in = (c.cur + 3 * a.step + a.stage) & 1;
-    const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
-    gptr<v2<R>> Ap = as_global<R>(c.A);
-    const Geo g = make_geo(c, i);
-#pragma unroll
-    for (int mu = 0, p = 0; mu < 4; mu++)
-#pragma unroll
-        for (int nu = mu + 1; nu < 4; nu++, p++) {
-            // rows 0,1 of U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
-            R2<R> P = r2_of(W(mu, i));
-            P = r2_mul_nn(P, W(nu, i + g.up(mu)));
-            P = r2_mul_nd(P, W(mu, i + g.up(nu)));
-            P = r2_mul_nd(P, W(nu, i));
-            const int k = c.tw[p];
-            if (k && g.n(mu) == 0 && g.n(nu) == 0) r2_scale(P, cconj(omega_pow<R>(k)));
-            R A8[8];
-            r2_proj_ah(P, R(1), A8);
-            st_alg8<R>(Ap, p, c.stride, i, A8);
-        }
-}
-
-template <class R>
-__device__ __forceinline__ void load_alg(gptr<const v2<R>> Ap, int stride, int p, int i, R out[8]) {
-    ld_alg8<R, false>(Ap, p, stride, i, out);     // read by two lanes: keep it cached
-}
-
-template <class R, int NE, int MU>
-__device__ __forceinline__ void split_body(const StageArgs &a, const CfgDesc &c, int i) {
-    const int in = (c.cur + 3 * a.step + a.stage) & 1;
-    const Links<R, NE> W{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
-    gptr<v2<R>> Wout = as_global<R>(in ? c.W[0] : c.W[1]);
-    gptr<v2<R>> X = as_global<R>(c.X);
-    gptr<const v2<R>> Ap = as_global<R>((const void *)c.A);
-    const double eps = a.step < c.n_full ? a.eps : c.eps_last;
-    const R beps = (R)(kRkB[a.stage] * eps);
-    const R ac = (R)kRkA[a.stage];
-    const Geo g = make_geo(c, i);
-
-    R om[8];   // P_ah(Omega_mu(n))
-#pragma unroll
-    for (int t = 0; t < 8; t++) om[t] = R(0);
-#pragma unroll
-    for (int nu = 0; nu < 4; nu++) {
-        if (nu == MU) continue;
-        const int p = MU < nu ? plane_index(MU, nu) : plane_index(nu, MU);
-        const R sg = MU < nu ? R(1) : R(-1);
-        R up[8], lo[8], cl[8];
-        load_alg(Ap, c.stride, p, i, up);
-        const int m = i + g.dn(nu);
-        load_alg(Ap, c.stride, p, m, lo);
-        conj_alg(W(nu, m), lo, cl);
-#pragma unroll
-        for (int t = 0; t < 8; t++) om[t] = fma(sg, up[t] - cl[t], om[t]);
-    }
-    // X = B eps F + A X_old with F = -P_ah(Omega)
-    Alg<R> Z;
-#pragma unroll
-    for (int t = 0; t < 8; t++) Z.a[t] = -beps * om[t];
-    gptr<v2<R>> xp = X + (size_t)(MU * 4) * c.stride;
-    const unsigned u = lane_off<R>(i);
-    if (a.stage > 0) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            cx<R> o = ld(xp + (size_t)k * c.stride, u);
-            Z.a[2 * k] = fma(ac, o.x, Z.a[2 * k]);
-            Z.a[2 * k + 1] = fma(ac, o.y, Z.a[2 * k + 1]);
-        }
-    }
-    if (a.stage < 2) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) st(xp + (size_t)k * c.stride, u, cx<R>{Z.a[2 * k], Z.a[2 * k + 1]});
-    }
-    const M3<R> E = su3_exp<R, NE == 9 ? 3 : 2>(Z);
-    const M3<R> U = W(MU, i);
-    M3<R> N;
-    if constexpr (NE == 9) {
-        N = mul_nn(E, U);
-    } else {
-        R2<R> r = r2_mul_nn(r2_of(E), U);
-#pragma unroll
-        for (int rr = 0; rr < 2; rr++)
-#pragma unroll
-            for (int j = 0; j < 3; j++) N.e[rr][j] = r.e[rr][j];
-    }
-    if (a.reunit) reunitarise(N);
-    store_link<R, NE>(Wout, c.stride, MU, i, N);
-}
-
-template <class R, int NE>
-__global__ __launch_bounds__(256) void split_link_kernel(StageArgs a) {
-    const int b = remap_block(blockIdx.x, a.n_tiles, a.xcd);
-    if (b >= a.n_tiles) return;
-    const int tile = b;
-    const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ci = find_cfg(a.tile_start, a.n_act, tile);
-    const CfgDesc c = a.cfgs[ci];
-    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
-    if (i >= c.V) return;
-    switch (mu) {
-        case 0: split_body<R, NE, 0>(a, c, i); break;
-        case 1: split_body<R, NE, 1>(a, c, i); break;
-        case 2: split_body<R, NE, 2>(a, c, i); break;
-        default: split_body<R, NE, 3>(a, c, i); break;
     }
 }
 
@@ -1033,6 +904,26 @@ __global__ __launch_bounds__(256) void slice_charge_kernel(const CfgDesc *__rest
         partials[(size_t)s * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Per-site densities of configuration ci: e(n) = sum_{mu<nu} Tr G^2 and
+// q(n) = (1/16 pi^2) Tr G G~, from the three dual plane pairs, written to
+// FP64 arrays in site order (either may be null).
+template <class R, int NE>
+__global__ __launch_bounds__(256) void density_kernel(const CfgDesc *__restrict__ cfgs, int ci,
+                                                      double *__restrict__ e_out,
+                                                      double *__restrict__ q_out) {
+    const CfgDesc c = cfgs[ci];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.V) return;
+    const Links<R, NE> W{as_global<R>((const void *)(c.cur ? c.W[1] : c.W[0])), c.stride};
+    const Geo g = make_geo(c, i);
+    double v0[4], v1[4], v2[4];
+    measure_pair<R, NE, 0>(W, c, g, v0);
+    measure_pair<R, NE, 1>(W, c, g, v1);
+    measure_pair<R, NE, 2>(W, c, g, v2);
+    if (e_out) e_out[i] = (v0[0] + v1[0]) + v2[0];
+    if (q_out) q_out[i] = (v0[1] + v1[1]) + v2[1];
+}
+
 __global__ void slice_finalize_kernel(const double *__restrict__ partials, int n_slices, int chunks,
                                       double *__restrict__ out) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1223,8 +1114,6 @@ const char *variant_name(int v) {
         case V_LINK: return "link";
         case V_SITE_XCD: return "site_xcd";
         case V_LINK_XCD: return "link_xcd";
-        case V_SPLIT: return "split";
-        case V_SPLIT_XCD: return "split_xcd";
         case V_SITE_ALG: return "site_alg";
         case V_SITE_ALG_XCD: return "site_alg_xcd";
         case V_SITE_ALG3: return "site_alg3";
@@ -1238,22 +1127,14 @@ const char *variant_name(int v) {
 }
 
 template <class R, int NE>
-static hipError_t launch_stage_t(int variant, int part, hipStream_t s, const StageArgs &a) {
-    const bool xcd = variant == V_SITE_XCD || variant == V_LINK_XCD || variant == V_SPLIT_XCD ||
-                     variant == V_SITE_ALG_XCD || variant == V_SITE_ALG3_XCD ||
+static hipError_t launch_stage_t(int variant, hipStream_t s, const StageArgs &a) {
+    const bool xcd = variant == V_SITE_XCD || variant == V_LINK_XCD || variant == V_SITE_ALG_XCD || variant == V_SITE_ALG3_XCD ||
                      variant == V_SITE_LDS_XCD || variant == V_SITE_PLQ_XCD;
     StageArgs b = a;
     b.xcd = xcd ? 1 : 0;
     const int site_blocks = xcd ? ((a.n_tiles + 3) / 4 + 7) / 8 * 8 : (a.n_tiles + 3) / 4;
     const int tile_blocks = xcd ? (a.n_tiles + 7) / 8 * 8 : a.n_tiles;
-    if (variant_is_split(variant)) {
-        if (part == 0)
-            hipLaunchKernelGGL((plaq_alg_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
-        else
-            hipLaunchKernelGGL((split_link_kernel<R, NE>), dim3(tile_blocks), dim3(256), 0, s, b);
-    } else if (part == 0) {
-        return hipSuccess;   // single-kernel variants have no part 0
-    } else if (variant == V_SITE || variant == V_SITE_XCD) {
+    if (variant == V_SITE || variant == V_SITE_XCD) {
         hipLaunchKernelGGL((stage_site_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
     } else if (variant == V_SITE_ALG || variant == V_SITE_ALG_XCD) {
         if constexpr (sizeof(R) == 8)
@@ -1273,14 +1154,14 @@ static hipError_t launch_stage_t(int variant, int part, hipStream_t s, const Sta
     return hipGetLastError();
 }
 
-hipError_t launch_stage(int variant, int part, Prec p, bool c12, hipStream_t s,
-                        const CfgDesc *cfgs, const int *tile_start, int n_act, int n_tiles,
-                        int step, int stage, double eps, int reunit) {
+hipError_t launch_stage(int variant, Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
+                        const int *tile_start, int n_act, int n_tiles, int step, int stage,
+                        double eps, int reunit_every) {
     if (n_tiles <= 0) return hipSuccess;
-    StageArgs a{cfgs, tile_start, n_act, n_tiles, step, stage, eps, reunit, 0};
-    if (p == P_F64) return launch_stage_t<double, 9>(variant, part, s, a);
-    if (c12) return launch_stage_t<float, 6>(variant, part, s, a);
-    return launch_stage_t<float, 9>(variant, part, s, a);
+    StageArgs a{cfgs, tile_start, n_act, n_tiles, step, stage, eps, reunit_every, 0};
+    if (p == P_F64) return launch_stage_t<double, 9>(variant, s, a);
+    if (c12) return launch_stage_t<float, 6>(variant, s, a);
+    return launch_stage_t<float, 9>(variant, s, a);
 }
 
 hipError_t launch_measure(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
@@ -1386,6 +1267,21 @@ hipError_t launch_slice_charge(Prec p, bool c12, hipStream_t s, const CfgDesc *c
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(slice_finalize_kernel, dim3((n_slices + 63) / 64), dim3(64), 0, s, partials,
                        n_slices, chunks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_densities(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs, int ci, int V,
+                            double *e_out, double *q_out) {
+    dim3 grid((V + 255) / 256);
+    if (p == P_F64)
+        hipLaunchKernelGGL((density_kernel<double, 9>), grid, dim3(256), 0, s, cfgs, ci, e_out,
+                           q_out);
+    else if (c12)
+        hipLaunchKernelGGL((density_kernel<float, 6>), grid, dim3(256), 0, s, cfgs, ci, e_out,
+                           q_out);
+    else
+        hipLaunchKernelGGL((density_kernel<float, 9>), grid, dim3(256), 0, s, cfgs, ci, e_out,
+                           q_out);
     return hipGetLastError();
 }
 

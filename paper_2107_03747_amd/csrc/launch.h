@@ -17,32 +17,29 @@ enum Variant {
     V_LINK = 1,       // one thread per link (wave-uniform mu), no sharing
     V_SITE_XCD = 2,   // V_SITE with XCD-contiguous tile order
     V_LINK_XCD = 3,   // V_LINK with XCD-contiguous tile order
-    V_SPLIT = 4,      // two kernels per stage: plaquette algebra A_{mu nu}(n), then
-                      // force from A and its conjugated neighbours + update
-    V_SPLIT_XCD = 5,  // V_SPLIT with XCD-contiguous tile order
-    V_SITE_ALG = 6,   // V_SITE with su(3) (8-real) force accumulators, upper
+    V_SITE_ALG = 4,   // V_SITE with su(3) (8-real) force accumulators, upper
                       // plaquettes projected from their two computed rows
-    V_SITE_ALG_XCD = 7,
-    V_SITE_ALG3 = 8,  // V_SITE_ALG capped at 168 registers (three waves per SIMD)
-    V_SITE_ALG3_XCD = 9,
-    V_SITE_LDS = 10,  // V_SITE_ALG reading links of the work-group's own 256 sites
+    V_SITE_ALG_XCD = 5,
+    V_SITE_ALG3 = 6,  // V_SITE_ALG capped at 168 registers (three waves per SIMD)
+    V_SITE_ALG3_XCD = 7,
+    V_SITE_LDS = 8,   // V_SITE_ALG reading links of the work-group's own sites
                       // from an LDS copy
-    V_SITE_LDS_XCD = 11,
-    V_SITE_PLQ = 12,  // V_SITE_ALG with the block's upper plaquettes kept in LDS and
+    V_SITE_LDS_XCD = 9,
+    V_SITE_PLQ = 10,  // V_SITE_ALG with the block's upper plaquettes kept in LDS and
                       // reused, conjugated, as in-block lower staple terms
-    V_SITE_PLQ_XCD = 13,
-    V_COUNT = 14
+    V_SITE_PLQ_XCD = 11,
+    V_COUNT = 12
 };
-inline bool variant_is_split(int v) { return v == V_SPLIT || v == V_SPLIT_XCD; }
 const char *variant_name(int v);
 
 // All launchers enqueue on `s` and return the hipError_t of the launch.
 // `tile_start` has n_act+1 entries (exec order); tiles are 64 sites.
-// One RK stage is part 1 (staples/force + update) of the variant, preceded for
-// the split variants by part 0 (plaquette algebra).
-hipError_t launch_stage(int variant, int part, Prec p, bool c12, hipStream_t s,
-                        const CfgDesc *cfgs, const int *tile_start, int n_act, int n_tiles,
-                        int step, int stage, double eps, int reunit);
+// One RK stage (staples, force, update of every link) is one launch;
+// reunit_every > 0 reunitarises in FP64 at the end of every reunit_every-th
+// step of each configuration (counted from its load, CfgDesc::reunit_phase).
+hipError_t launch_stage(int variant, Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
+                        const int *tile_start, int n_act, int n_tiles, int step, int stage,
+                        double eps, int reunit_every);
 
 hipError_t launch_measure(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
                           const int *tile_start, int n_cfg, int n_tiles, const MeasSlot *slots,
@@ -70,6 +67,11 @@ hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void 
 hipError_t launch_slice_charge(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs, int ci,
                                int dir, int n_slices, int slice_sites, double *partials,
                                double *out);
+
+// Per-site e(n) and q(n) of config ci (exec-order descriptor at cfgs[ci]), V
+// doubles each in site order; either output may be null.
+hipError_t launch_densities(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs, int ci, int V,
+                            double *e_out, double *q_out);
 
 // One Monte Carlo launch: the links of direction mu on the sites of parity
 // par (0 even, 1 odd) of every configuration, heat bath (heatbath = 1) or

@@ -9,11 +9,10 @@
 //               that one 16-byte access moves two complex numbers
 //               (entry_index);
 //   X           RK accumulator [mu (4)][slot (4)][site (stride)] of complex R:
-//               slots 0..2 = X01, X02, X12, slot 3 = (Im X00, Im X11);
-//   A           plaquette algebra [plane (6)][slot (4)][site (stride)] of
-//               complex R, same slot format: A_{mu nu}(n) = P_ah(Z^* P_{mu nu}(n))
-//               for mu < nu (written and read within one RK stage by the
-//               two-kernel "split" stage variants).
+//               slots 0..2 = X01, X02, X12, slot 3 = (Im X00, Im X11); FP32
+//               pairs the slots, [mu][pair (2)][site][2].
+// Bytes per site: FP64 full 2 x 576 + 256 = 1408, FP32 full 2 x 288 + 128 =
+// 704, FP32 12-real 2 x 192 + 128 = 512.
 // `stride` is the site count rounded up to a multiple of 256 so that every
 // entry plane starts 256-byte aligned and a wavefront's 64 consecutive sites
 // read 64 consecutive complex numbers (fully coalesced).
@@ -40,11 +39,12 @@ struct CfgDesc {
     int32_t cur;          // which W buffer holds the links at step 0 of this flow
     int32_t n_full;       // full steps of size eps this flow
     int32_t n_steps;      // n_full + (short final step ? 1 : 0)
+    int32_t reunit_phase; // steps since the load, before this flow, mod reunit_every
+    int32_t pad0;
     double eps_last;      // size of the short final step (0 if none)
     double t0;            // flow time at the start of this flow
     void *W[2];
     void *X;
-    void *A;
 };
 
 // Index (in complex elements) of entry e of link (mu, site i) in a link buffer.

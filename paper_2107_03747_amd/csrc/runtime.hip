@@ -51,9 +51,10 @@ struct CfgHost {
     int V;
     int stride;
     int tiles;
-    size_t offW[2], offX, offA;
+    size_t offW[2], offX;
     int cur = 0;
     double t = 0;
+    long long steps = 0;     // RK steps since the links were loaded (reunitarisation schedule)
     bool loaded = false;
 };
 
@@ -123,24 +124,22 @@ Layout make_layout(int32_t n_cfg, const tgf_geom *g, tgf_storage st, int nc = 3,
     for (int c = 0; c < n_cfg; c++) {
         CfgHost &h = L.cfg[c];
         size_t wb = e * 4 * NE * (size_t)h.stride;
-        // SU(N): X is a full N x N matrix per link and there is no A buffer
+        // SU(N): X is a full N x N matrix per link
         size_t xb = e * 4 * (general ? NE : 4) * (size_t)h.stride;
-        size_t ab = general ? 0 : e * 6 * 4 * (size_t)h.stride;
         h.offW[0] = o; o = align_up(o + wb, 256);
         h.offW[1] = o; o = align_up(o + wb, 256);
         h.offX = o;    o = align_up(o + xb, 256);
-        h.offA = o;    o = align_up(o + ab, 256);
     }
     L.total = o;
     return L;
 }
 
 struct Launch {
-    int kind;      // 0 stage (part 1), 1 measure, 2 finalize, 3 zero flag, 4 stage part 0
+    int kind;      // 0 stage, 1 measure, 2 finalize, 3 zero flag
     int grid;      // tiles (stage/measure) or configs (finalize)
     int n_act;
     int step, stage;
-    int reunit;
+    int reunit;    // stage launches: reunit_every (FP32 storages), else 0
     int event;     // measurement event index (slot table row)
     bool operator==(const Launch &o) const {
         return kind == o.kind && grid == o.grid && n_act == o.n_act && step == o.step &&
@@ -215,7 +214,6 @@ void fill_desc(const tgf_ctx *c, const CfgHost &h, int user, CfgDesc &d) {
     d.W[0] = c->ws + h.offW[0];
     d.W[1] = c->ws + h.offW[1];
     d.X = c->ws + h.offX;
-    d.A = c->ws + h.offA;
 }
 
 bool on_grid(double t, double dt) {
@@ -260,13 +258,11 @@ tgf_status run_launches(tgf_ctx *c, const std::vector<Launch> &ls, double eps, b
     auto issue = [&](const Launch &l) -> hipError_t {
         switch (l.kind) {
             case 0:
-            case 4:
                 if (c->general)
                     return launch_stage_sun(c->nc, variant, s, c->d_desc(), c->d_tiles(), l.n_act,
                                             l.grid, l.step, l.stage, eps);
-                return launch_stage(variant, l.kind == 0 ? 1 : 0, c->prec(), c->c12(), s,
-                                    c->d_desc(), c->d_tiles(), l.n_act, l.grid, l.step, l.stage,
-                                    eps, l.reunit);
+                return launch_stage(variant, c->prec(), c->c12(), s, c->d_desc(), c->d_tiles(),
+                                    l.n_act, l.grid, l.step, l.stage, eps, l.reunit);
             case 1:
                 if (c->general)
                     return launch_measure_sun(c->nc, variant, s, c->d_desc(), c->d_tiles(),
@@ -364,8 +360,11 @@ tgf_status run_check(tgf_ctx *c, int cfg, const void *src, bool canon, double ou
 
 // Upload descriptors + tile prefix of the given exec order.
 // half_sites: the tiles cover the V/2 sites of one parity (Monte Carlo).
+// reunit_every: the flow's reunitarisation period, for each configuration's
+// phase (steps done since its load, modulo the period).
 tgf_status upload_tables(tgf_ctx *c, const std::vector<int> &order, const std::vector<Plan> *plans,
-                         std::vector<int> &tile_start, bool half_sites = false) {
+                         std::vector<int> &tile_start, bool half_sites = false,
+                         int reunit_every = 0) {
     const int n = (int)order.size();
     tile_start.assign(n + 1, 0);
     for (int k = 0; k < n; k++) {
@@ -379,6 +378,8 @@ tgf_status upload_tables(tgf_ctx *c, const std::vector<int> &order, const std::v
     CfgDesc *dd = (CfgDesc *)c->h_stage;
     for (int k = 0; k < n; k++) {
         fill_desc(c, c->L.cfg[order[k]], order[k], dd[k]);
+        if (reunit_every > 0)
+            dd[k].reunit_phase = (int)(c->L.cfg[order[k]].steps % reunit_every);
         if (plans) {
             const Plan &p = (*plans)[order[k]];
             dd[k].n_full = p.n_full;
@@ -525,6 +526,7 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
         CfgHost &h = c->L.cfg[cfgs[k]];
         h.cur = 0;
         h.t = t0[k];
+        h.steps = 0;
         h.loaded = true;
     }
     return TGF_OK;
@@ -574,6 +576,36 @@ tgf_status tgf_get_time(tgf_ctx *c, int32_t cfg, double *t) {
     if ((s = check_cfg(c, cfg))) return s;
     if (!t) return fail(TGF_E_INVAL, "t is NULL");
     *t = c->L.cfg[cfg].t;
+    return TGF_OK;
+}
+
+tgf_status tgf_densities(tgf_ctx *c, int32_t cfg, double *e_dev, double *q_dev) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if ((s = check_cfg(c, cfg))) return s;
+    if (c->general) return fail(TGF_E_UNSUPPORTED, "densities: SU(3) contexts only");
+    const CfgHost &h = c->L.cfg[cfg];
+    if (!h.loaded) return fail(TGF_E_STATE, "config not loaded");
+    if (!e_dev && !q_dev) return TGF_OK;
+    std::vector<int> order(c->n_cfg);
+    for (int k = 0; k < c->n_cfg; k++) order[k] = k;
+    std::vector<int> ts;
+    if ((s = upload_tables(c, order, nullptr, ts))) return s;
+    HIP_TRY(launch_densities(c->prec(), c->c12(), c->stream, c->d_desc(), cfg, h.V, e_dev, q_dev));
+    return TGF_OK;
+}
+
+tgf_status tgf_link_buffer(tgf_ctx *c, int32_t cfg, size_t *offset, size_t *bytes) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if ((s = check_cfg(c, cfg))) return s;
+    if (!offset || !bytes) return fail(TGF_E_INVAL, "NULL argument");
+    const CfgHost &h = c->L.cfg[cfg];
+    if (!h.loaded) return fail(TGF_E_STATE, "config not loaded");
+    *offset = h.offW[h.cur];
+    *bytes = cx_bytes(c->st) * 4 * (size_t)c->ne() * (size_t)h.stride;
     return TGF_OK;
 }
 
@@ -678,8 +710,10 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
     for (auto &v : ev) n_events += v.empty() ? 0 : 1;
     if (n_events > kMaxRows) return fail(TGF_E_SIZE, "too many measurement events");
 
+    const bool fp32 = c->st != TGF_F64_FULL;
+    const int reunit_every = fp32 ? p->reunit_every : 0;
     std::vector<int> ts;
-    if ((s = upload_tables(c, order, &plans, ts))) return s;
+    if ((s = upload_tables(c, order, &plans, ts, false, reunit_every))) return s;
     // slot table
     if ((s = ensure_stage(c, sizeof(MeasSlot) * (size_t)std::max(n_events, 1) * n))) return s;
     MeasSlot *ms = (MeasSlot *)c->h_stage;
@@ -716,15 +750,9 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
         ls.push_back(Launch{2, n, n, 0, 0, 0, e});
     };
     add_meas(0);
-    const bool fp32 = c->st != TGF_F64_FULL;
-    const bool split = variant_is_split(c->effective_variant());
     for (int k = 0; k < max_steps; k++) {
         int na = active[k];
-        int reunit = (fp32 && p->reunit_every > 0 && (k + 1) % p->reunit_every == 0) ? 1 : 0;
-        for (int st = 0; st < 3; st++) {
-            if (split) ls.push_back(Launch{4, ts[na], na, k, st, 0, -1});
-            ls.push_back(Launch{0, ts[na], na, k, st, st == 2 ? reunit : 0, -1});
-        }
+        for (int st = 0; st < 3; st++) ls.push_back(Launch{0, ts[na], na, k, st, reunit_every, -1});
         add_meas(k + 1);
     }
 
@@ -752,23 +780,17 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
             HIP_TRY(hipEventElapsedTime(&ms_, c->events[2 * k], c->events[2 * k + 1]));
             const Launch &l = ls[k];
             double sites = 0;
-            if (l.kind == 0 || l.kind == 4)
+            if (l.kind == 0)
                 for (int j = 0; j < l.n_act; j++) sites += c->L.cfg[order[j]].V;
             // algorithmic bytes: every element an operation touches, once
-            const double links = 4.0 * NE * e, xs = 4.0 * c->x_entries() * e,
-                         as = 6.0 * 4 * e;
+            const double links = 4.0 * NE * e, xs = 4.0 * c->x_entries() * e;
             if (l.kind == 0) {
                 tm.stage_ms += ms_;
                 tm.stage_launches++;
-                // links read + written, X written (stage 0), read+written (1), read (2),
-                // and for the split variants the plaquette algebra read
+                // links read + written, X written (stage 0), read+written (1), read (2)
                 double xfac = l.stage == 1 ? 2.0 : 1.0;
-                tm.stage_bytes += sites * (2.0 * links + xfac * xs + (split ? as : 0.0));
+                tm.stage_bytes += sites * (2.0 * links + xfac * xs);
                 tm.stage_site_updates += sites / 3.0;
-            } else if (l.kind == 4) {
-                tm.aux_ms += ms_;
-                tm.aux_launches++;
-                tm.aux_bytes += sites * (links + as);   // links read, A written
             } else if (l.kind == 1 || l.kind == 2) {
                 tm.measure_ms += ms_;
                 tm.measure_launches++;
@@ -792,6 +814,7 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
         CfgHost &h = c->L.cfg[k];
         h.cur = (h.cur + 3 * plans[k].n_steps) & 1;
         h.t = std::max(p->t_end[k], h.t);
+        h.steps += plans[k].n_steps;
     }
     if (flag) return fail(TGF_E_NONFINITE, "non-finite observable during the flow");
     return TGF_OK;
@@ -874,7 +897,10 @@ tgf_status tgf_mc(tgf_ctx *c, double b, int32_t n_hybrid, int32_t n_or, uint64_t
                     HIP_TRY(launch_mc(c->stream, c->d_desc(), c->d_tiles(), c->n_cfg,
                                       ts[c->n_cfg], mu, par, o == 0 ? 1 : 0, beta, seed, sweep));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    for (int k = 0; k < c->n_cfg; k++) c->L.cfg[k].t = 0;
+    for (int k = 0; k < c->n_cfg; k++) {
+        c->L.cfg[k].t = 0;
+        c->L.cfg[k].steps = 0;
+    }
     return TGF_OK;
 }
 
@@ -969,11 +995,8 @@ tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path) {
         if (c->general)
             return launch_stage_sun(c->nc, v, c->stream, c->d_desc(), c->d_tiles(), n, ts[n], 0,
                                     0, 0.01);
-        hipError_t err = hipSuccess;
-        for (int part = 0; part < 2 && err == hipSuccess; part++)
-            err = launch_stage(v, part, c->prec(), c->c12(), c->stream, c->d_desc(),
-                               c->d_tiles(), n, ts[n], 0, 0, 0.01, 0);
-        return err;
+        return launch_stage(v, c->prec(), c->c12(), c->stream, c->d_desc(), c->d_tiles(), n,
+                            ts[n], 0, 0, 0.01, 0);
     };
     for (int v = 0; v < c->variant_count(); v++) {
         // the plaquette-sharing variants take a lower staple term from LDS or

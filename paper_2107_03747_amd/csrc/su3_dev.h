@@ -371,17 +371,21 @@ __device__ constexpr double kInvK[25] = {
     1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17,
     1.0 / 18, 1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24};
 
-// exp(X) for X in su(3), by Cayley-Hamilton: with Q = -i X (Hermitian,
+// exp(X) - 1 for X in su(3), by Cayley-Hamilton: with Q = -i X (Hermitian,
 // traceless), Q^3 = c1 Q + c0 with c1 = Tr(Q^2)/2, c0 = det Q, so every power
 // Q^k = alpha_k + beta_k Q + gamma_k Q^2 and exp(iQ) = f0 + f1 Q + f2 Q^2 with
 // f_j the exponential series of the coefficient recursion
 //   alpha' = gamma c0, beta' = alpha + gamma c1, gamma' = beta.
 // The series runs until the remainder bound rho^k/k! (rho = ||Q||_F) drops
 // below the working precision; for rho > 1 the argument is halved s times and
-// the result squared s times.  ROWS = 2 returns rows 0 and 1 only (enough to
-// update a 12-real link), unless squarings are needed.
+// the result squared s times ((1 + D)^2 - 1 = 2D + D^2).
+//
+// The identity is left out (f0 starts at 0) so that the caller can form
+// exp(X) U as U + (D U) with one rounding per entry (mul_add_expm1).
+// ROWS = 2 returns rows 0 and 1 only (enough to update a 12-real link),
+// unless squarings are needed.
 template <class R, int ROWS = 3>
-__device__ __forceinline__ M3<R> su3_exp(const Alg<R> &X) {
+__device__ __forceinline__ M3<R> su3_expm1(const Alg<R> &X) {
     // Q = -i X
     R q00 = X.a[6], q11 = X.a[7], q22 = -(X.a[6] + X.a[7]);
     cx<R> q01 = {X.a[1], -X.a[0]}, q02 = {X.a[3], -X.a[2]}, q12 = {X.a[5], -X.a[4]};
@@ -409,9 +413,10 @@ __device__ __forceinline__ M3<R> su3_exp(const Alg<R> &X) {
     const R re3 = t.x * q02.x + t.y * q02.y;
     const R c0 = q00 * q11 * q22 + R(2) * re3 - q00 * n12 - q11 * n02 - q22 * n01;
 
-    // series: term k holds alpha_k/k!, beta_k/k!, gamma_k/k!, weight i^k
+    // series: term k holds alpha_k/k!, beta_k/k!, gamma_k/k!, weight i^k; the
+    // k = 0 term (the identity) is not added
     R al = R(1), be = R(0), ga = R(0);
-    cx<R> f0 = {R(1), R(0)}, f1 = {R(0), R(0)}, f2 = {R(0), R(0)};
+    cx<R> f0 = {R(0), R(0)}, f1 = {R(0), R(0)}, f2 = {R(0), R(0)};
     const R rho = sqrt(fro2);
     R bound = R(1);
 #pragma unroll
@@ -445,25 +450,56 @@ __device__ __forceinline__ M3<R> su3_exp(const Alg<R> &X) {
     cx<R> s12 = {(q11 + q22) * q12.x, (q11 + q22) * q12.y};
     s12 = cmadd_cn(s12, q01, q02);
 
-    // E = f0 + f1 Q + f2 Q^2
+    // D = (f0 - 1) + f1 Q + f2 Q^2
     auto ent = [&](cx<R> q, cx<R> sq) { return cmadd(cmul(f1, q), f2, sq); };
     auto dia = [&](R q, R sq) {
         return cx<R>{f0.x + f1.x * q + f2.x * sq, f0.y + f1.y * q + f2.y * sq};
     };
-    M3<R> E;
-    E.e[0][0] = dia(q00, s00);
-    E.e[0][1] = ent(q01, s01);
-    E.e[0][2] = ent(q02, s02);
-    E.e[1][0] = ent(cconj(q01), cconj(s01));
-    E.e[1][1] = dia(q11, s11);
-    E.e[1][2] = ent(q12, s12);
+    M3<R> D;
+    D.e[0][0] = dia(q00, s00);
+    D.e[0][1] = ent(q01, s01);
+    D.e[0][2] = ent(q02, s02);
+    D.e[1][0] = ent(cconj(q01), cconj(s01));
+    D.e[1][1] = dia(q11, s11);
+    D.e[1][2] = ent(q12, s12);
     if (ROWS == 3 || s > 0) {
-        E.e[2][0] = ent(cconj(q02), cconj(s02));
-        E.e[2][1] = ent(cconj(q12), cconj(s12));
-        E.e[2][2] = dia(q22, s22);
+        D.e[2][0] = ent(cconj(q02), cconj(s02));
+        D.e[2][1] = ent(cconj(q12), cconj(s12));
+        D.e[2][2] = dia(q22, s22);
     }
-    for (int i = 0; i < s; i++) E = mul_nn(E, E);
-    return E;
+    for (int i = 0; i < s; i++) {
+        M3<R> D2 = mul_nn(D, D);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+                D.e[a][b] = cadd(D2.e[a][b], cadd(D.e[a][b], D.e[a][b]));
+    }
+    return D;
+}
+
+// Rows 0 .. ROWS-1 of exp(X) U = U + (D U) with D = exp(X) - 1 (su3_expm1).
+// The increment D U is summed on its own (its entries are of the size of X,
+// so FP32 keeps its second-order part -|X|^2 U / 2 to a relative 1e-7) and
+// added to U last, one rounding per entry.  Any other order loses that part:
+// a diagonal 1 - |X|^2/2 rounds to 1 when |X|^2 < 2^-24, and a multiply-add
+// chain started from U's entry rounds after its first-order term, after which
+// the second-order term is below half an ulp of the running sum and dropped.
+// Either way every link gains norm |X|^2 per stage, which shows as a
+// plaquette offset growing by ~1e-7 per step until the next reunitarisation.
+template <class R, int ROWS>
+__device__ __forceinline__ M3<R> mul_add_expm1(const M3<R> &D, const M3<R> &U) {
+    M3<R> N;
+#pragma unroll
+    for (int r = 0; r < ROWS; r++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            cx<R> s = cmul(D.e[r][0], U.e[0][j]);
+            s = cmadd(s, D.e[r][1], U.e[1][j]);
+            s = cmadd(s, D.e[r][2], U.e[2][j]);
+            N.e[r][j] = cadd(U.e[r][j], s);
+        }
+    return N;
 }
 
 }  // namespace tgf

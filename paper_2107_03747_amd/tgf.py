@@ -92,8 +92,6 @@ class tgf_flow_params(ctypes.Structure):
 class tgf_timing(ctypes.Structure):
     _fields_ = [("stage_ms", ctypes.c_double), ("stage_launches", ctypes.c_int64),
                 ("stage_bytes", ctypes.c_double), ("stage_site_updates", ctypes.c_double),
-                ("aux_ms", ctypes.c_double), ("aux_launches", ctypes.c_int64),
-                ("aux_bytes", ctypes.c_double),
                 ("measure_ms", ctypes.c_double), ("measure_launches", ctypes.c_int64)]
 
 
@@ -115,6 +113,9 @@ _sig = {
     "tgf_load_links_all": (_st, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double)]),
     "tgf_store_links": (_st, [_P, _I, _P]),
     "tgf_get_time": (_st, [_P, _I, ctypes.POINTER(ctypes.c_double)]),
+    "tgf_densities": (_st, [_P, _I, _P, _P]),
+    "tgf_link_buffer": (_st, [_P, _I, ctypes.POINTER(ctypes.c_size_t),
+                              ctypes.POINTER(ctypes.c_size_t)]),
     "tgf_measure": (_st, [_P, ctypes.POINTER(tgf_obs)]),
     "tgf_flow": (_st, [_P, ctypes.POINTER(tgf_flow_params), ctypes.POINTER(tgf_obs), _I,
                        ctypes.POINTER(_I)]),
@@ -280,6 +281,23 @@ class Flow:
         v = ctypes.c_double()
         check(tgf_get_time(self._ctx, int(cfg), ctypes.byref(v)))
         return v.value
+
+    def densities(self, cfg):
+        """Per-site e(n) and q(n) of cfg (FP64 device tensors [V], site order)."""
+        t = self.torch
+        V = int(np.prod(self.dims[cfg]))
+        e = t.empty(V, dtype=t.float64, device=self.device)
+        q = t.empty(V, dtype=t.float64, device=self.device)
+        self._sync_in()
+        check(tgf_densities(self._ctx, int(cfg), _ptr(e), _ptr(q)))
+        t.cuda.current_stream(self.device).wait_stream(self.stream)
+        return e, q
+
+    def link_buffer(self, cfg):
+        """(byte offset in the workspace, bytes) of cfg's stored links."""
+        off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+        check(tgf_link_buffer(self._ctx, int(cfg), ctypes.byref(off), ctypes.byref(nb)))
+        return int(off.value), int(nb.value)
 
     def measure(self):
         """-> structured numpy array [n_cfg] with OBS_FIELDS."""

@@ -48,10 +48,15 @@ def test_workspace_sizes_scale_with_storage():
     f64 = tgf.workspace_bytes(g, "f64")
     f32 = tgf.workspace_bytes(g, "f32")
     c12 = tgf.workspace_bytes(g, "f32c12")
-    # two link buffers + X + plaquette algebra: (2*4*9 + 4*4 + 6*4) complex/site,
-    # 16 bytes each in FP64, 8 in FP32
-    assert f64 - f32 == pytest.approx(V * (2 * 4 * 9 + 4 * 4 + 6 * 4) * 8, abs=4096)
+    # two link buffers + X: (2*4*9 + 4*4) complex/site, 16 bytes each in FP64, 8 in FP32
+    assert f64 - f32 == pytest.approx(V * (2 * 4 * 9 + 4 * 4) * 8, abs=4096)
     assert f32 - c12 == pytest.approx(V * (2 * 4 * 3 * 8), abs=4096)
+    # per-site storage: 1408 / 704 / 512 bytes (the shared tables are a small
+    # constant on top: descriptors, partials, rows, schedule)
+    g2 = [(8, 8, 24, 48)]
+    for st, per_site in (("f64", 1408), ("f32", 704), ("f32c12", 512)):
+        assert tgf.workspace_bytes(g2, st) - tgf.workspace_bytes(g, st) == pytest.approx(
+            V * per_site, rel=0.01)
 
 
 FAKE = 1 << 40   # an aligned address; validation never dereferences it
@@ -97,6 +102,12 @@ def test_state_and_argument_errors_before_any_enqueue():
         assert tgf.tgf_autotune(ctx, None) == tgf.TGF_E_STATE
         d2 = (ctypes.c_double * 2)()
         assert tgf.tgf_unitarity(ctx, 0, d2) == tgf.TGF_E_STATE
+        off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+        assert tgf.tgf_link_buffer(ctx, 0, ctypes.byref(off), ctypes.byref(nb)) == tgf.TGF_E_STATE
+        assert tgf.tgf_link_buffer(ctx, 0, None, ctypes.byref(nb)) == tgf.TGF_E_INVAL
+        assert tgf.tgf_link_buffer(ctx, 2, ctypes.byref(off), ctypes.byref(nb)) == tgf.TGF_E_INVAL
+        assert tgf.tgf_densities(ctx, 0, ctypes.c_void_p(FAKE), None) == tgf.TGF_E_STATE
+        assert tgf.tgf_densities(ctx, -1, ctypes.c_void_p(FAKE), None) == tgf.TGF_E_INVAL
         # bad flow parameters
         for eps in (0.0, -0.01, float("nan"), float("inf")):
             p = tgf.tgf_flow_params(eps, te, 0.0, 0, 0)
@@ -132,6 +143,7 @@ def test_null_context_is_rejected():
     obs = (tgf.tgf_obs * 1)()
     assert tgf.tgf_measure(None, obs) == tgf.TGF_E_INVAL
     assert tgf.tgf_load_links(None, 0, ctypes.c_void_p(FAKE), 0.0) == tgf.TGF_E_INVAL
+    assert tgf.tgf_densities(None, 0, None, None) == tgf.TGF_E_INVAL
     tgf.tgf_destroy(None)
 
 

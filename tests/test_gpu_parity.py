@@ -2,11 +2,16 @@
 
 Bars (relative error of t^2 E over rows with t > 0): <= 1e-12 for the FP64
 path, <= 1e-5 for both FP32 storages (the stated precision targets).  The
-plaquette and Q bars are derived from the arithmetic: plaquette <= 1e-13
-(FP64) / 4e-6 (FP32) absolute -- an FP32 link entry is rounded to 2^-24 at
-each of the 3 stages per step, a random walk of about sqrt(216) * 6e-8 ~ 1e-6
-over the 72 steps of the 8x8x24x24 flow, and the plaquette is an O(1) trace
-of four such links -- and Q <= 1e-10 / 1e-4 absolute.  Workloads: synthetic seeded links of the shapes
+plaquette bar is 1e-13 (FP64) / 1e-6 (FP32) absolute and Q's 1e-10 / 1e-4.
+The plaquette is an average over 6V plaquettes, so unbiased FP32 roundings
+of the links cancel in it; what remains is a systematic drift of the link
+norms off SU(3).  The link update is formed as U + (exp(X) - 1) U, so its
+roundings have no preferred direction (forming exp(X) first rounded its
+diagonal 1 - |X|^2/2 to 1 whenever |X|^2 < 2^-24 and grew every link's norm
+by |X|^2 per stage, a plaquette offset of ~1e-6 after ten steps).  The FP32
+unitarity bar, 2e-6, is the largest defect of a link after <= 30 stages of
+unbiased roundings since the last reunitarisation (sqrt(30) x 1e-7 per
+stage, about 3.5 standard deviations over the 147 456 links).  Workloads: synthetic seeded links of the shapes
 the paper flows (L x L x 3L x 3L, twist n_01 = 1, sec. 3.1), eps = 0.01.
 Full sizes beyond the oracle's reach are covered by properties in
 test_gpu_properties.py.
@@ -27,8 +32,8 @@ from paper_2107_03747_amd import gen, tgf          # noqa: E402
 oracle.set_threads(16)
 
 TOL = {"f64": dict(t2E=1e-12, plaq=1e-13, Q=1e-10),
-       "f32": dict(t2E=1e-5, plaq=4e-6, Q=1e-4),
-       "f32c12": dict(t2E=1e-5, plaq=4e-6, Q=1e-4)}
+       "f32": dict(t2E=1e-5, plaq=1e-6, Q=1e-4),
+       "f32c12": dict(t2E=1e-5, plaq=1e-6, Q=1e-4)}
 COL = {n: k for k, n in enumerate(tgf.OBS_FIELDS)}
 
 
@@ -107,7 +112,8 @@ def test_d2_parity(d2, storage):
                        reunit=10 if storage != "f64" else 0)
     compare(rows[:, 0], ref, storage, "D2")
     du, dd = f.unitarity(0)
-    bar = 1e-13 if storage == "f64" else 1e-5   # see test_fp32_tracks_fp64_full_flow_d3
+    say(f"  D2 {storage}: unitarity defects {du:.3g} {dd:.3g}")
+    bar = 1e-13 if storage == "f64" else 2e-6
     assert du < bar and dd < bar
 
 
