@@ -287,6 +287,29 @@ tgf_status tgf_susceptibility(const double *Q, int32_t n, double V, double *chi,
 /* Message of the last failing statistics call ("" if none). */
 const char *tgf_stats_last_error(void);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * measurement of tgf_measure (E, t2E, plaquette, Q, action; FP64) on links the
+ * caller holds in canonical layout, with no context and no workspace.
+ *   geom:      extents (each >= 2, at most TGF_NOALLOC_MAX_SITES sites in
+ *              all, else TGF_E_SIZE) and twist (entries 0..2);
+ *   links_dev: complex128 [d3][d2][d1][d0][4][3][3], device memory (not
+ *              checked for SU(3));
+ *   t:         flow time written to out (t2E = t^2 E), finite, >= 0;
+ *   out_dev:   one tgf_obs in device memory, written by the last kernel;
+ *   hip_stream: hipStream_t (NULL = the null stream) of the current device.
+ * Nothing is allocated (no hipMalloc, no pinned staging): the reduction
+ * partials live in a fixed device array of the library (18 MiB, one per GPU,
+ * held until the process ends), fully rewritten by every call.  Calls that
+ * overlap on one GPU race on that array; serialise them (one stream).
+ * Arguments are checked on the host; then two kernels are enqueued and the
+ * call returns without synchronising.  A non-finite sum shows as non-finite
+ * entries of *out_dev (there is no status word).  The result equals that of
+ * tgf_measure on a TGF_F64_FULL context holding the same links. */
+#define TGF_NOALLOC_MAX_SITES 12582912
+tgf_status tgf_measure_noalloc(const tgf_geom *geom, const void *links_dev, double t,
+                               tgf_obs *out_dev, void *hip_stream);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char *tgf_last_error(void);
 

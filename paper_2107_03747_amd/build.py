@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtgf.so")
-SOURCES = ["kernels.hip", "mc.hip", "sun.hip", "runtime.hip", "stats.cpp"]
+SOURCES = ["kernels.hip", "mc.hip", "sun.hip", "runtime.hip", "noalloc.hip", "stats.cpp"]
 ARCH = os.environ.get("TGF_OFFLOAD_ARCH", "gfx950")
 
 

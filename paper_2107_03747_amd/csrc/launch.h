@@ -100,6 +100,9 @@ hipError_t launch_unpack_sun(int nc, hipStream_t s, const void *W, void *dst, in
 hipError_t launch_check_sun(int nc, bool canon, hipStream_t s, const void *src, int V, int stride,
                             double *partials, double *out);
 
+// Set the thread-local message returned by tgf_last_error.
+void set_last_error(const char *msg);
+
 hipError_t launch_fill_int(hipStream_t s, int *dst, int n, int value);
 hipError_t launch_copy(hipStream_t s, void *dst, const void *src, size_t bytes);
 

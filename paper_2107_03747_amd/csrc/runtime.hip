@@ -400,6 +400,8 @@ tgf_status upload_tables(tgf_ctx *c, const std::vector<int> &order, const std::v
 
 }  // namespace
 
+void tgf::set_last_error(const char *msg) { g_err = msg ? msg : ""; }
+
 // ===========================================================================
 // C ABI
 

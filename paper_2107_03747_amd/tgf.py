@@ -71,6 +71,7 @@ STORAGES = {"f64": TGF_F64_FULL, "f32": TGF_F32_FULL, "f32c12": TGF_F32_C12}
 TGF_NO_GRAPH = 1
 TGF_TIMING = 2
 TGF_MAX_ROWS = 4096
+TGF_NOALLOC_MAX_SITES = 12582912
 
 PAPER_TWIST = (1, 0, 0, 0, 0, 0)
 
@@ -140,6 +141,7 @@ _sig = {
     "tgf_susceptibility": (_st, [ctypes.POINTER(ctypes.c_double), _I, ctypes.c_double,
                                  ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)]),
+    "tgf_measure_noalloc": (_st, [ctypes.POINTER(tgf_geom), _P, ctypes.c_double, _P, _P]),
     "tgf_stats_last_error": (ctypes.c_char_p, []),
     "tgf_last_error": (ctypes.c_char_p, []),
     "tgf_destroy": (None, [_P]),
