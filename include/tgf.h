@@ -211,14 +211,30 @@ tgf_status tgf_get_timing(tgf_ctx *c, tgf_timing *out);
  * reduction): out[2].  Synchronises. */
 tgf_status tgf_unitarity(tgf_ctx *c, int32_t cfg, double *out);
 
-/* Time the candidate stage-kernel variants on the loaded links (a few stages
- * each, links restored afterwards) and keep the fastest for this context.
- * Candidates are the variants whose result for a configuration does not
- * depend on the other configurations of the batch (all but "site_plq" and
- * "site_plq_xcd", which tgf_set_variant still selects).
- * cache_path (may be NULL): a text file of "key variant" lines read before
- * and appended after tuning.  Synchronises. */
+/* Tune the stage kernel on the loaded links (stage 0 timed with HIP events,
+ * links restored afterwards; the batched ensemble of the paper's Table A.1
+ * mixes extents, so shapes are tuned per extent):
+ *   (1) the variant, timed on the whole batch, among the XCD-ordered site and
+ *       link kernels (the LDS-staged one first); a candidate replaces the
+ *       current choice only when it is more than 2% faster;
+ *   (2) for the LDS-staged variants, the work-group shape of each class of
+ *       configurations with equal extents: whole (n0, n1) planes (the
+ *       default, tgf_get_block) against 256 consecutive sites, timed on that
+ *       class alone, with the same 2% rule.
+ * The plaquette-sharing variants, whose rounding depends on the other
+ * configurations of a work-group, are never chosen (tgf_set_variant still
+ * selects them).  cache_path (may be NULL): a text file of "key value" lines
+ * (one per variant choice and per class shape) read before and appended
+ * after tuning.  Synchronises. */
 tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path);
+
+/* Sites per work-group of the LDS-staged variants for configuration cfg
+ * (64..256).  Default: whole (n0, n1) planes -- the largest multiple of
+ * d0 d1 not above 256 when that is at least 128 (L = 6: 252, L = 10: 200,
+ * L = 12: 144), else 256.  tgf_set_block(c, cfg, 0) restores the default.
+ * Results do not depend on the shape beyond rounding order. */
+tgf_status tgf_get_block(tgf_ctx *c, int32_t cfg, int32_t *sites);
+tgf_status tgf_set_block(tgf_ctx *c, int32_t cfg, int32_t sites);
 
 /* Select a stage-kernel variant by index (0 .. tgf_variant_count()-1), or
  * -1 for the built-in default ("site_lds_xcd", the LDS-staged site kernel;

@@ -69,6 +69,8 @@ struct StageArgs {
     const int *tile_start;
     int n_act;
     int n_tiles;
+    const int *blk_start;   // LDS-staged variants: work-groups of CfgDesc::blk sites
+    int n_blocks;
     int step;
     int stage;
     double eps;
@@ -274,9 +276,10 @@ __device__ __forceinline__ void wave_update(const LK &W, gptr<v2<R>> Wout, gptr<
 template <class R, int NE, class LK>
 __device__ __forceinline__ void site_wave_work(const LK &W, gptr<v2<R>> Wout, gptr<v2<R>> X,
                                                const CfgDesc &c, const Geo &g, R beps, R ac,
-                                               const StageArgs &a) {
+                                               const StageArgs &a, int nw) {
+    // nw: active lanes of this wave, holding sites tb .. tb + nw - 1
     const int i = g.i;
-    const int tb = i - (int)(threadIdx.x & 63);        // first site of this wave's tile
+    const int tb = i - (int)(threadIdx.x & 63);        // first site of this wave
     Alg<R> f[4];
 #pragma unroll
     for (int mu = 0; mu < 4; mu++)
@@ -301,7 +304,7 @@ __device__ __forceinline__ void site_wave_work(const LK &W, gptr<v2<R>> Wout, gp
                 f[nu].a[t] -= A8[t];
             }
             const int imn = i + g.dn(nu);
-            if (__all((unsigned)(imn - tb) < 64u)) {
+            if (__all((unsigned)(imn - tb) < (unsigned)nw)) {
                 R an[8], cc[8];
 #pragma unroll
                 for (int t = 0; t < 8; t++) an[t] = __shfl(A8[t], imn - tb);
@@ -311,7 +314,7 @@ __device__ __forceinline__ void site_wave_work(const LK &W, gptr<v2<R>> Wout, gp
                 done |= 1u << (4 * mu + nu);
             }
             const int imm = i + g.dn(mu);
-            if (__all((unsigned)(imm - tb) < 64u)) {
+            if (__all((unsigned)(imm - tb) < (unsigned)nw)) {
                 R an[8], cc[8];
 #pragma unroll
                 for (int t = 0; t < 8; t++) an[t] = __shfl(A8[t], imm - tb);
@@ -350,17 +353,18 @@ __device__ __forceinline__ void site_alg_body(const StageArgs &a) {
 }
 
 // ---------------------------------------------------------------------------
-// LDS-staged site variant.  A work-group owns 256 consecutive sites of one
-// configuration; it first copies their four links into LDS as 16-byte units
-// ([mu][unit][site]: FP32 entry pairs, and entry 8 alone for the full
+// LDS-staged site variant.  A work-group owns blk consecutive sites of one
+// configuration (blk <= 256 per configuration, CfgDesc::blk: whole (n0, n1)
+// planes where they fit, so that the neighbours in directions 0 and 1 are
+// always in the block); it first copies their four links into LDS as 16-byte
+// units ([mu][unit][site]: FP32 entry pairs, and entry 8 alone for the full
 // storage; FP64 one complex entry per unit), then every link a wave needs is
 // read from LDS when all of its active lanes find the link's site inside the
-// block, and from global memory otherwise.  With the site order n0 fastest,
-// the block holds whole (n0, n1) planes when l^2 divides 256, so the
-// neighbours in directions 0 and 1, and most of those in direction 2, come
-// from LDS.  LDS per work-group: 48 KB (FP32 12-real), 72 KB (FP32 full),
-// 144 KB (FP64).  (Staging full matrices for the 12-real storage, so that
-// its third rows are rebuilt once per link, ran 15% slower.)
+// block, and from global memory otherwise.  Wave w holds sites base + 64 w +
+// lane (lanes past the block end are idle).  LDS per work-group: 48 KB (FP32
+// 12-real), 72 KB (FP32 full), 144 KB (FP64).  (Staging full matrices for the
+// 12-real storage, so that its third rows are rebuilt once per link, ran 15%
+// slower.)
 
 template <class R, int NE>
 struct StagedLinks {
@@ -370,13 +374,11 @@ struct StagedLinks {
     const U16 *s16;           // [mu][unit][kBlock]
     const v2<R> *s8;          // [mu][kBlock], FP32 full storage entry 8
     int base;                 // first site of the block
-    int staged;               // work-group uniform
-    // a link of this lane's own site: in LDS whenever the block is staged
-    __device__ __forceinline__ M3<R> own(int mu, int i) const {
-        return fetch(mu, i, staged != 0);
-    }
+    int nblk;                 // sites in the block
+    // a link of this lane's own site: always in LDS
+    __device__ __forceinline__ M3<R> own(int mu, int i) const { return fetch(mu, i, true); }
     __device__ __forceinline__ M3<R> operator()(int mu, int j) const {
-        return fetch(mu, j, staged && __all((unsigned)(j - base) < (unsigned)kBlock));
+        return fetch(mu, j, __all((unsigned)(j - base) < (unsigned)nblk));
     }
     __device__ __forceinline__ M3<R> fetch(int mu, int j, bool from_lds) const {
         // the 16-byte units come from LDS or from global memory; the matrix
@@ -430,46 +432,38 @@ __device__ __forceinline__ void site_lds_body(const StageArgs &a) {
     __shared__ U16 s16[4 * NU * kBlock];
     __shared__ v2<R> s8[kE8 ? 4 * kBlock : 1];
 
-    const int nb = (a.n_tiles + 3) >> 2;
-    const int b = remap_block(blockIdx.x, nb, a.xcd);
-    if (b >= nb) return;                                   // whole work-group
-    const int t0 = b * 4;
-    const int tile = t0 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // stage only when the four tiles exist and belong to one configuration
-    // (work-group uniform, so every wave reaches the barrier below)
-    const int ci0 = find_cfg(a.tile_start, a.n_act, t0);
-    const int staged = t0 + 3 < a.n_tiles && find_cfg(a.tile_start, a.n_act, t0 + 3) == ci0;
-    if (!staged && tile >= a.n_tiles) return;
-    const int ci = staged ? ci0 : find_cfg(a.tile_start, a.n_act, tile);
+    const int b = remap_block(blockIdx.x, a.n_blocks, a.xcd);
+    if (b >= a.n_blocks) return;                           // whole work-group
+    const int ci = find_cfg(a.blk_start, a.n_act, b);      // work-group uniform
     const CfgDesc c = a.cfgs[ci];
-    const int i = (tile - a.tile_start[ci]) * kTile + (threadIdx.x & 63);
+    const int base = (b - a.blk_start[ci]) * c.blk;
+    const int nblk = min(c.blk, c.V - base);               // sites base .. base + nblk - 1
+    const int i = base + (int)threadIdx.x;
 
     const int in = (c.cur + 3 * a.step + a.stage) & 1;
     const Links<R, NE> G{as_global<R>((const void *)(in ? c.W[1] : c.W[0])), c.stride};
-    if (staged) {
-        if (i < c.V) {
-            // unit u of link (mu, i) sits at byte (mu NE stride 2 sizeof(R)) +
-            // u stride 16 + 16 i (the FP32 pairs of entry_index; FP64 entries)
-            gptr<const char> q = (gptr<const char>)G.p;
-            const size_t pl = (size_t)c.stride * 16u;
-            const unsigned u = (unsigned)i * 16u;
+    if ((int)threadIdx.x < nblk) {
+        // unit u of link (mu, i) sits at byte (mu NE stride 2 sizeof(R)) +
+        // u stride 16 + 16 i (the FP32 pairs of entry_index; FP64 entries)
+        gptr<const char> q = (gptr<const char>)G.p;
+        const size_t pl = (size_t)c.stride * 16u;
+        const unsigned u = (unsigned)i * 16u;
 #pragma unroll
-            for (int mu = 0; mu < 4; mu++) {
-                gptr<const char> qm = q + (size_t)(mu * NE) * c.stride * (2 * sizeof(R));
+        for (int mu = 0; mu < 4; mu++) {
+            gptr<const char> qm = q + (size_t)(mu * NE) * c.stride * (2 * sizeof(R));
 #pragma unroll
-                for (int e = 0; e < NU; e++)
-                    s16[(mu * NU + e) * kBlock + threadIdx.x] = *(gptr<const U16>)(qm + e * pl + u);
-                if constexpr (kE8) {
-                    const cx<R> z = ld(G.p + (size_t)(mu * 9 + 8) * c.stride, lane_off<R>(i));
-                    s8[mu * kBlock + threadIdx.x] = v2<R>{z.x, z.y};
-                }
+            for (int e = 0; e < NU; e++)
+                s16[(mu * NU + e) * kBlock + threadIdx.x] = *(gptr<const U16>)(qm + e * pl + u);
+            if constexpr (kE8) {
+                const cx<R> z = ld(G.p + (size_t)(mu * 9 + 8) * c.stride, lane_off<R>(i));
+                s8[mu * kBlock + threadIdx.x] = v2<R>{z.x, z.y};
             }
         }
-        __syncthreads();
     }
-    if (i >= c.V) return;
+    __syncthreads();
+    if ((int)threadIdx.x >= nblk) return;
 
-    const StagedLinks<R, NE> W{G, s16, s8, (t0 - a.tile_start[ci]) * kTile, staged};
+    const StagedLinks<R, NE> W{G, s16, s8, base, nblk};
     gptr<v2<R>> Wout = as_global<R>(in ? c.W[0] : c.W[1]);
     gptr<v2<R>> X = as_global<R>(c.X);
     const double eps = a.step < c.n_full ? a.eps : c.eps_last;
@@ -477,10 +471,12 @@ __device__ __forceinline__ void site_lds_body(const StageArgs &a) {
     const R ac = (R)kRkA[a.stage];
     // 12-real storage reuses in-wave plaquettes (stage launch -1.4%); for the
     // full storages the plain site_alg_work measured faster
-    if constexpr (sizeof(R) == 4 && NE == 6)
-        site_wave_work<R, NE>(W, Wout, X, c, make_geo(c, i), beps, ac, a);
-    else
+    if constexpr (sizeof(R) == 4 && NE == 6) {
+        const int nw = min(64, nblk - (int)(threadIdx.x & ~63u));
+        site_wave_work<R, NE>(W, Wout, X, c, make_geo(c, i), beps, ac, a, nw);
+    } else {
         site_alg_work<R, NE>(W, Wout, X, c, make_geo(c, i), beps, ac, a);
+    }
 }
 
 // Waves per SIMD: FP32 12-real three (168 registers, a few spilled; three
@@ -997,6 +993,7 @@ static hipError_t launch_stage_t(int variant, hipStream_t s, const StageArgs &a)
     b.xcd = xcd ? 1 : 0;
     const int site_blocks = xcd ? ((a.n_tiles + 3) / 4 + 7) / 8 * 8 : (a.n_tiles + 3) / 4;
     const int tile_blocks = xcd ? (a.n_tiles + 7) / 8 * 8 : a.n_tiles;
+    const int lds_blocks = xcd ? (a.n_blocks + 7) / 8 * 8 : a.n_blocks;
     if (variant == V_SITE || variant == V_SITE_XCD) {
         hipLaunchKernelGGL((stage_site_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
     } else if (variant == V_SITE_ALG || variant == V_SITE_ALG_XCD) {
@@ -1008,7 +1005,9 @@ static hipError_t launch_stage_t(int variant, hipStream_t s, const StageArgs &a)
     } else if (variant == V_SITE_ALG3 || variant == V_SITE_ALG3_XCD) {
         hipLaunchKernelGGL((stage_site_alg3_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
     } else if (variant == V_SITE_LDS || variant == V_SITE_LDS_XCD) {
-        hipLaunchKernelGGL((stage_site_lds_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
+        if (lds_blocks > 0)
+            hipLaunchKernelGGL((stage_site_lds_kernel<R, NE>), dim3(lds_blocks), dim3(256), 0, s,
+                               b);
     } else if (variant == V_SITE_PLQ || variant == V_SITE_PLQ_XCD) {
         hipLaunchKernelGGL((stage_site_plq_kernel<R, NE>), dim3(site_blocks), dim3(256), 0, s, b);
     } else {
@@ -1018,10 +1017,11 @@ static hipError_t launch_stage_t(int variant, hipStream_t s, const StageArgs &a)
 }
 
 hipError_t launch_stage(int variant, Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
-                        const int *tile_start, int n_act, int n_tiles, int step, int stage,
-                        double eps, int reunit_every) {
+                        const int *tile_start, int n_act, int n_tiles, const int *blk_start,
+                        int n_blocks, int step, int stage, double eps, int reunit_every) {
     if (n_tiles <= 0) return hipSuccess;
-    StageArgs a{cfgs, tile_start, n_act, n_tiles, step, stage, eps, reunit_every, 0};
+    StageArgs a{cfgs, tile_start, n_act, n_tiles, blk_start, n_blocks, step, stage, eps,
+                reunit_every, 0};
     if (p == P_F64) return launch_stage_t<double, 9>(variant, s, a);
     if (c12) return launch_stage_t<float, 6>(variant, s, a);
     return launch_stage_t<float, 9>(variant, s, a);

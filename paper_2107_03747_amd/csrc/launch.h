@@ -34,12 +34,15 @@ const char *variant_name(int v);
 
 // All launchers enqueue on `s` and return the hipError_t of the launch.
 // `tile_start` has n_act+1 entries (exec order); tiles are 64 sites.
+// `blk_start` (n_act+1 entries) numbers the work-groups of the LDS-staged
+// variants: CfgDesc::blk sites each, never more than one configuration.
 // One RK stage (staples, force, update of every link) is one launch;
 // reunit_every > 0 reunitarises in FP64 at the end of every reunit_every-th
 // step of each configuration (counted from its load, CfgDesc::reunit_phase).
 hipError_t launch_stage(int variant, Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
-                        const int *tile_start, int n_act, int n_tiles, int step, int stage,
-                        double eps, int reunit_every);
+                        const int *tile_start, int n_act, int n_tiles, const int *blk_start,
+                        int n_blocks, int step, int stage, double eps, int reunit_every);
+inline bool variant_is_lds(int v) { return v == V_SITE_LDS || v == V_SITE_LDS_XCD; }
 
 hipError_t launch_measure(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs,
                           const int *tile_start, int n_cfg, int n_tiles, const MeasSlot *slots,

@@ -51,6 +51,7 @@ struct CfgHost {
     int V;
     int stride;
     int tiles;
+    int blk;                 // sites per LDS-staged work-group (default_block, or tuned)
     size_t offW[2], offX;
     int cur = 0;
     double t = 0;
@@ -59,13 +60,31 @@ struct CfgHost {
 };
 
 struct Layout {
-    size_t off_desc, off_tiles, off_flag, off_check, off_partials, off_rows, off_meas, off_cfg0;
+    size_t off_desc, off_tiles, off_blocks, off_flag, off_check, off_partials, off_rows, off_meas,
+        off_cfg0;
     size_t total;
     int total_tiles;
     std::vector<CfgHost> cfg;
 };
 
 int ne_of(tgf_storage st) { return st == TGF_F32_C12 ? 6 : 9; }
+
+// Sites per work-group of the LDS-staged stage variants: whole (n0, n1) planes
+// (so that every neighbour in directions 0 and 1 lies in the block) when at
+// least two of them fill half of the 256 threads; otherwise 256.  For the
+// L x L x 3L x 3L boxes: L = 6 -> 252, 8 -> 256, 10 -> 200, 12 -> 144.
+int default_block(const int d[4]) {
+    const int plane = d[0] * d[1];
+    if (plane > kBlock) return kBlock;
+    const int k = kBlock / plane;
+    return k * plane >= kBlock / 2 ? k * plane : kBlock;
+}
+
+// The other candidate the autotuner times for a configuration (0 if none).
+int other_block(const int d[4]) {
+    const int b = default_block(d);
+    return b == kBlock ? 0 : kBlock;
+}
 size_t cx_bytes(tgf_storage st) { return st == TGF_F64_FULL ? 16 : 8; }
 
 // nc: colours; general: the SU(N) storage (N^2 entries per link)
@@ -105,12 +124,14 @@ Layout make_layout(int32_t n_cfg, const tgf_geom *g, tgf_storage st, int nc = 3,
         for (int k = 0; k < 6; k++) h.tw[k] = g[c].twist[k];
         h.stride = (int)align_up((size_t)h.V, 256);
         h.tiles = (h.V + 63) / 64;
+        h.blk = default_block(h.d);
         tiles += h.tiles;
     }
     L.total_tiles = tiles;
     size_t o = 0;
     L.off_desc = o;     o = align_up(o + sizeof(CfgDesc) * n_cfg, 256);
     L.off_tiles = o;    o = align_up(o + sizeof(int) * (n_cfg + 1), 256);
+    L.off_blocks = o;   o = align_up(o + sizeof(int) * (n_cfg + 1), 256);
     L.off_flag = o;     o = align_up(o + 64, 256);
     L.off_check = o;    o = align_up(o + 64, 256);
     // measurement: 4 doubles per (tile, plane pair); unitarity check: 2 per tile
@@ -141,9 +162,10 @@ struct Launch {
     int step, stage;
     int reunit;    // stage launches: reunit_every (FP32 storages), else 0
     int event;     // measurement event index (slot table row)
+    int blocks;    // stage launches: work-groups of the LDS-staged variants
     bool operator==(const Launch &o) const {
         return kind == o.kind && grid == o.grid && n_act == o.n_act && step == o.step &&
-               stage == o.stage && reunit == o.reunit && event == o.event;
+               stage == o.stage && reunit == o.reunit && event == o.event && blocks == o.blocks;
     }
 };
 
@@ -172,6 +194,7 @@ struct tgf_ctx {
 
     CfgDesc *d_desc() { return (CfgDesc *)(ws + L.off_desc); }
     int *d_tiles() { return (int *)(ws + L.off_tiles); }
+    int *d_blocks() { return (int *)(ws + L.off_blocks); }
     int *d_flag() { return (int *)(ws + L.off_flag); }
     double *d_check() { return (double *)(ws + L.off_check); }
     double *d_partials() { return (double *)(ws + L.off_partials); }
@@ -211,6 +234,7 @@ void fill_desc(const tgf_ctx *c, const CfgHost &h, int user, CfgDesc &d) {
     d.user = user;
     d.cur = h.cur;
     d.t0 = h.t;
+    d.blk = h.blk;
     d.W[0] = c->ws + h.offW[0];
     d.W[1] = c->ws + h.offW[1];
     d.X = c->ws + h.offX;
@@ -262,7 +286,8 @@ tgf_status run_launches(tgf_ctx *c, const std::vector<Launch> &ls, double eps, b
                     return launch_stage_sun(c->nc, variant, s, c->d_desc(), c->d_tiles(), l.n_act,
                                             l.grid, l.step, l.stage, eps);
                 return launch_stage(variant, c->prec(), c->c12(), s, c->d_desc(), c->d_tiles(),
-                                    l.n_act, l.grid, l.step, l.stage, eps, l.reunit);
+                                    l.n_act, l.grid, c->d_blocks(), l.blocks, l.step, l.stage,
+                                    eps, l.reunit);
             case 1:
                 if (c->general)
                     return launch_measure_sun(c->nc, variant, s, c->d_desc(), c->d_tiles(),
@@ -364,15 +389,18 @@ tgf_status run_check(tgf_ctx *c, int cfg, const void *src, bool canon, double ou
 // phase (steps done since its load, modulo the period).
 tgf_status upload_tables(tgf_ctx *c, const std::vector<int> &order, const std::vector<Plan> *plans,
                          std::vector<int> &tile_start, bool half_sites = false,
-                         int reunit_every = 0) {
+                         int reunit_every = 0, std::vector<int> *blk_start = nullptr) {
     const int n = (int)order.size();
     tile_start.assign(n + 1, 0);
+    std::vector<int> bs(n + 1, 0);
     for (int k = 0; k < n; k++) {
         const CfgHost &h = c->L.cfg[order[k]];
         const int tiles = half_sites ? (h.V / 2 + 63) / 64 : h.tiles;
         tile_start[k + 1] = tile_start[k] + tiles;
+        bs[k + 1] = bs[k] + (h.V + h.blk - 1) / h.blk;
     }
-    size_t bytes = sizeof(CfgDesc) * n + sizeof(int) * (n + 1);
+    if (blk_start) *blk_start = bs;
+    size_t bytes = sizeof(CfgDesc) * n + 2 * sizeof(int) * (n + 1);
     tgf_status st = ensure_stage(c, bytes);
     if (st) return st;
     CfgDesc *dd = (CfgDesc *)c->h_stage;
@@ -389,9 +417,13 @@ tgf_status upload_tables(tgf_ctx *c, const std::vector<int> &order, const std::v
     }
     int *ti = (int *)(c->h_stage + sizeof(CfgDesc) * n);
     memcpy(ti, tile_start.data(), sizeof(int) * (n + 1));
+    int *bi = ti + (n + 1);
+    memcpy(bi, bs.data(), sizeof(int) * (n + 1));
     HIP_TRY(hipMemcpyAsync(c->d_desc(), dd, sizeof(CfgDesc) * n, hipMemcpyHostToDevice,
                            c->stream));
     HIP_TRY(hipMemcpyAsync(c->d_tiles(), ti, sizeof(int) * (n + 1), hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->d_blocks(), bi, sizeof(int) * (n + 1), hipMemcpyHostToDevice,
                            c->stream));
     // the staging buffer is reused by the caller: wait for the copies
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -714,8 +746,8 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
 
     const bool fp32 = c->st != TGF_F64_FULL;
     const int reunit_every = fp32 ? p->reunit_every : 0;
-    std::vector<int> ts;
-    if ((s = upload_tables(c, order, &plans, ts, false, reunit_every))) return s;
+    std::vector<int> ts, bs;
+    if ((s = upload_tables(c, order, &plans, ts, false, reunit_every, &bs))) return s;
     // slot table
     if ((s = ensure_stage(c, sizeof(MeasSlot) * (size_t)std::max(n_events, 1) * n))) return s;
     MeasSlot *ms = (MeasSlot *)c->h_stage;
@@ -742,19 +774,20 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
     }
 
     std::vector<Launch> ls;
-    ls.push_back(Launch{3, 1, 0, 0, 0, 0, 0});
+    ls.push_back(Launch{3, 1, 0, 0, 0, 0, 0, 0});
     auto add_meas = [&](int k) {
         int e = event_of_step[k];
         if (e < 0) return;
         // configs measured at this event are all still "active" up to step k, but a
         // config whose flow ended earlier is never measured here, so n_cfg covers it
-        ls.push_back(Launch{1, ts[n], n, 3 * k, 0, 0, e});
-        ls.push_back(Launch{2, n, n, 0, 0, 0, e});
+        ls.push_back(Launch{1, ts[n], n, 3 * k, 0, 0, e, 0});
+        ls.push_back(Launch{2, n, n, 0, 0, 0, e, 0});
     };
     add_meas(0);
     for (int k = 0; k < max_steps; k++) {
         int na = active[k];
-        for (int st = 0; st < 3; st++) ls.push_back(Launch{0, ts[na], na, k, st, reunit_every, -1});
+        for (int st = 0; st < 3; st++)
+            ls.push_back(Launch{0, ts[na], na, k, st, reunit_every, -1, bs[na]});
         add_meas(k + 1);
     }
 
@@ -939,22 +972,37 @@ tgf_status tgf_set_variant(tgf_ctx *c, int32_t v) {
 
 int32_t tgf_get_variant(tgf_ctx *c) { return c ? c->effective_variant() : -1; }
 
-static std::string tune_key(tgf_ctx *c) {
-    std::ostringstream k;
+static std::string arch_name() {
     hipDeviceProp_t prop;
     int dev = 0;
+    std::string a = "unknown";
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-        k << prop.gcnArchName;
-    else
-        k << "unknown";
-    k << "/st" << (int)c->st;
+        a = prop.gcnArchName;
+    for (char &ch : a)
+        if (ch == ' ') ch = '_';
+    return a;
+}
+
+// Cache key of the variant choice: device, storage, colours, every extent.
+static std::string tune_key(tgf_ctx *c) {
+    std::ostringstream k;
+    k << arch_name() << "/st" << (int)c->st;
     if (c->general) k << "/nc" << c->nc;
     for (auto &h : c->L.cfg) k << "/" << h.d[0] << "x" << h.d[1] << "x" << h.d[2] << "x" << h.d[3];
-    std::string s = k.str();
-    for (char &ch : s)
-        if (ch == ' ') ch = '_';
-    return s;
+    return k.str();
 }
+
+// Cache key of one extent class's work-group shape under a variant.
+static std::string block_key(tgf_ctx *c, int variant, const int d[4]) {
+    std::ostringstream k;
+    k << arch_name() << "/st" << (int)c->st << "/v" << variant << "/blk/" << d[0] << "x" << d[1]
+      << "x" << d[2] << "x" << d[3];
+    return k.str();
+}
+
+// A timed candidate replaces the incumbent only when faster by this fraction,
+// so that choices within timing noise stay with the default.
+constexpr float kTuneMargin = 0.02f;
 
 tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path) {
     g_err.clear();
@@ -963,70 +1011,145 @@ tgf_status tgf_autotune(tgf_ctx *c, const char *cache_path) {
     for (int k = 0; k < c->n_cfg; k++)
         if (!c->L.cfg[k].loaded)
             return fail(TGF_E_STATE, "config " + std::to_string(k) + " not loaded");
-    const std::string key = tune_key(c);
+    std::vector<std::pair<std::string, int>> cache;
     if (cache_path) {
         std::ifstream in(cache_path);
         std::string k2;
         int v;
-        while (in >> k2 >> v)
-            if (k2 == key && v >= 0 && v < c->variant_count()) {
-                c->variant = v;
-                return TGF_OK;
-            }
+        while (in >> k2 >> v) cache.push_back({k2, v});
     }
-    // time stage 0 (reads the current links, writes the other buffer and X:
-    // the loaded state is not modified) for every variant
-    const int n = c->n_cfg;
-    std::vector<int> order(n);
-    for (int k = 0; k < n; k++) order[k] = k;
-    std::vector<Plan> plans(n);
-    for (int k = 0; k < n; k++) {
-        plans[k].n_full = 1;
-        plans[k].n_steps = 1;
-        plans[k].eps_last = 0;
+    auto cached = [&](const std::string &key, int &out) {
+        for (auto it = cache.rbegin(); it != cache.rend(); ++it)
+            if (it->first == key) { out = it->second; return true; }
+        return false;
+    };
+    std::vector<std::pair<std::string, int>> found;
+
+    // classes of configurations with equal extents (the work-group shape is tuned per class)
+    std::vector<std::vector<int>> classes;
+    for (int k = 0; k < c->n_cfg; k++) {
+        bool placed = false;
+        for (auto &cl : classes) {
+            const CfgHost &h0 = c->L.cfg[cl[0]], &h = c->L.cfg[k];
+            if (std::equal(h.d, h.d + 4, h0.d)) { cl.push_back(k); placed = true; break; }
+        }
+        if (!placed) classes.push_back({k});
     }
-    std::vector<int> ts;
-    if ((s = upload_tables(c, order, &plans, ts))) return s;
+
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    int best = -1;
-    float best_ms = 1e30f;
-    const int reps = 5;
-    auto stage0 = [&](int v) {
-        if (c->general)
-            return launch_stage_sun(c->nc, v, c->stream, c->d_desc(), c->d_tiles(), n, ts[n], 0,
-                                    0, 0.01);
-        return launch_stage(v, c->prec(), c->c12(), c->stream, c->d_desc(), c->d_tiles(), n,
-                            ts[n], 0, 0, 0.01, 0);
-    };
-    for (int v = 0; v < c->variant_count(); v++) {
-        // the plaquette-sharing variants take a lower staple term from LDS or
-        // form it directly depending on which configurations share a
-        // work-group, so a configuration's result would depend on the batch
-        // around it; they are selected only explicitly (tgf_set_variant)
-        if (!c->general && (v == V_SITE_PLQ || v == V_SITE_PLQ_XCD)) continue;
-        hipError_t err = stage0(v);
-        if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
-        for (int r = 0; r < reps && err == hipSuccess; r++) err = stage0(v);
-        if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms_ = 0;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms_, e0, e1);
-        if (err != hipSuccess) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return fail(TGF_E_HIP, std::string("autotune: ") + hipGetErrorString(err));
+    // stage 0 of the given configurations (reads the current links, writes the
+    // other buffer and X, so the loaded state is not modified): the least of
+    // three averages over five launches, in ms
+    auto time_stage0 = [&](int v, const std::vector<int> &order, float &ms) -> tgf_status {
+        const int n = (int)order.size();
+        std::vector<Plan> plans(c->n_cfg);
+        for (auto &p : plans) { p.n_full = 1; p.n_steps = 1; p.eps_last = 0; }
+        std::vector<int> ts, bs;
+        tgf_status st = upload_tables(c, order, &plans, ts, false, 0, &bs);
+        if (st) return st;
+        auto launch = [&]() {
+            if (c->general)
+                return launch_stage_sun(c->nc, v, c->stream, c->d_desc(), c->d_tiles(), n, ts[n],
+                                        0, 0, 0.01);
+            return launch_stage(v, c->prec(), c->c12(), c->stream, c->d_desc(), c->d_tiles(), n,
+                                ts[n], c->d_blocks(), bs[n], 0, 0, 0.01, 0);
+        };
+        ms = 1e30f;
+        HIP_TRY(launch());
+        for (int trial = 0; trial < 3; trial++) {
+            HIP_TRY(hipEventRecord(e0, c->stream));
+            for (int r = 0; r < 5; r++) HIP_TRY(launch());
+            HIP_TRY(hipEventRecord(e1, c->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float t = 0;
+            HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t / 5);
         }
-        if (ms_ < best_ms) { best_ms = ms_; best = v; }
+        return TGF_OK;
+    };
+    auto done = [&](tgf_status st) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return st;
+    };
+
+    // (1) the stage variant, on the whole batch.  Candidates: for SU(N) every
+    // rows-per-lane build; for SU(3) the XCD-ordered kernels (the plain block
+    // order of the same kernel runs as fast with more L2-miss traffic), not the
+    // plaquette-sharing one, whose rounding depends on which configurations
+    // share a work-group.
+    std::vector<int> all(c->n_cfg);
+    for (int k = 0; k < c->n_cfg; k++) all[k] = k;
+    const std::string vkey = tune_key(c);
+    int best = -1;
+    if (!cached(vkey, best) || best < 0 || best >= c->variant_count()) {
+        std::vector<int> cand;
+        if (c->general)
+            for (int v = 0; v < c->variant_count(); v++) cand.push_back(v);
+        else
+            cand = {V_SITE_LDS_XCD, V_SITE_ALG_XCD, V_SITE_ALG3_XCD, V_SITE_XCD, V_LINK_XCD};
+        float best_ms = 0;
+        for (size_t j = 0; j < cand.size(); j++) {
+            float ms = 0;
+            if ((s = time_stage0(cand[j], all, ms))) return done(s);
+            if (j == 0 || ms < best_ms * (1.0f - kTuneMargin)) { best = cand[j]; best_ms = ms; }
+        }
+        found.push_back({vkey, best});
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     c->variant = best;
-    if (cache_path) {
-        std::ofstream o(cache_path, std::ios::app);
-        if (o) o << key << " " << best << "\n";
+
+    // (2) the work-group shape of the LDS-staged variants, per extent class,
+    // timed on that class alone
+    if (!c->general && variant_is_lds(best)) {
+        for (auto &cl : classes) {
+            CfgHost &h0 = c->L.cfg[cl[0]];
+            const std::string bkey = block_key(c, best, h0.d);
+            int blk = 0;
+            if (!cached(bkey, blk) || blk < 1 || blk > kBlock) {
+                blk = default_block(h0.d);
+                const int alt = other_block(h0.d);
+                if (alt) {
+                    float ms_def = 0, ms_alt = 0;
+                    for (int k : cl) c->L.cfg[k].blk = blk;
+                    if ((s = time_stage0(best, cl, ms_def))) return done(s);
+                    for (int k : cl) c->L.cfg[k].blk = alt;
+                    if ((s = time_stage0(best, cl, ms_alt))) return done(s);
+                    if (ms_alt < ms_def * (1.0f - kTuneMargin)) blk = alt;
+                }
+                found.push_back({bkey, blk});
+            }
+            for (int k : cl) c->L.cfg[k].blk = blk;
+        }
     }
+    if (cache_path && !found.empty()) {
+        std::ofstream o(cache_path, std::ios::app);
+        if (o)
+            for (auto &f : found) o << f.first << " " << f.second << "\n";
+    }
+    return done(TGF_OK);
+}
+
+tgf_status tgf_get_block(tgf_ctx *c, int32_t cfg, int32_t *sites) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if ((s = check_cfg(c, cfg))) return s;
+    if (!sites) return fail(TGF_E_INVAL, "sites is NULL");
+    *sites = c->L.cfg[cfg].blk;
+    return TGF_OK;
+}
+
+tgf_status tgf_set_block(tgf_ctx *c, int32_t cfg, int32_t sites) {
+    g_err.clear();
+    tgf_status s = check_ctx(c);
+    if (s) return s;
+    if ((s = check_cfg(c, cfg))) return s;
+    if (sites == 0) sites = default_block(c->L.cfg[cfg].d);
+    if (sites < 64 || sites > kBlock)
+        return fail(TGF_E_INVAL, "sites per work-group must be 64..256 (0 = default)");
+    c->L.cfg[cfg].blk = sites;
     return TGF_OK;
 }
 

@@ -123,6 +123,8 @@ _sig = {
     "tgf_get_timing": (_st, [_P, ctypes.POINTER(tgf_timing)]),
     "tgf_unitarity": (_st, [_P, _I, ctypes.POINTER(ctypes.c_double)]),
     "tgf_autotune": (_st, [_P, ctypes.c_char_p]),
+    "tgf_get_block": (_st, [_P, _I, ctypes.POINTER(_I)]),
+    "tgf_set_block": (_st, [_P, _I, _I]),
     "tgf_set_variant": (_st, [_P, _I]),
     "tgf_get_variant": (_I, [_P]),
     "tgf_variant_count": (_I, []),
@@ -361,6 +363,16 @@ class Flow:
 
     def set_variant(self, v):
         check(tgf_set_variant(self._ctx, int(v)))
+
+    def block(self, cfg):
+        """Sites per work-group of the LDS-staged variants for cfg."""
+        v = ctypes.c_int32()
+        check(tgf_get_block(self._ctx, int(cfg), ctypes.byref(v)))
+        return int(v.value)
+
+    def set_block(self, cfg, sites):
+        """Pin cfg's LDS work-group shape (0 = the default whole-plane shape)."""
+        check(tgf_set_block(self._ctx, int(cfg), int(sites)))
 
     @property
     def variant(self):

@@ -139,6 +139,30 @@ def test_state_and_argument_errors_before_any_enqueue():
         tgf.tgf_destroy(ctx)
 
 
+def test_block_shapes_default_to_whole_planes():
+    """LDS work-groups hold whole (n0, n1) planes of the L x L x 3L x 3L boxes
+    when at least half the 256 threads get work, else 256 sites."""
+    dims = [(6, 6, 18, 18), (8, 8, 24, 24), (10, 10, 30, 30), (12, 12, 36, 36), (16, 16, 48, 48),
+            (32, 32, 96, 96), (3, 5, 4, 7), (9, 20, 4, 4), (20, 20, 4, 4)]
+    want = [252, 256, 200, 144, 256, 256, 255, 180, 256]
+    rc, ctx, _ = make_ctx(tgf.TGF_F32_C12, dims)
+    assert rc == tgf.TGF_OK
+    try:
+        v = ctypes.c_int32()
+        for k, w in enumerate(want):
+            assert tgf.tgf_get_block(ctx, k, ctypes.byref(v)) == tgf.TGF_OK and v.value == w, k
+        assert tgf.tgf_set_block(ctx, 0, 256) == tgf.TGF_OK
+        assert tgf.tgf_get_block(ctx, 0, ctypes.byref(v)) == tgf.TGF_OK and v.value == 256
+        assert tgf.tgf_set_block(ctx, 0, 0) == tgf.TGF_OK
+        assert tgf.tgf_get_block(ctx, 0, ctypes.byref(v)) == tgf.TGF_OK and v.value == 252
+        for bad in (63, 257, -1):
+            assert tgf.tgf_set_block(ctx, 0, bad) == tgf.TGF_E_INVAL
+        assert tgf.tgf_set_block(ctx, len(dims), 256) == tgf.TGF_E_INVAL
+        assert tgf.tgf_get_block(ctx, 0, None) == tgf.TGF_E_INVAL
+    finally:
+        tgf.tgf_destroy(ctx)
+
+
 def test_null_context_is_rejected():
     obs = (tgf.tgf_obs * 1)()
     assert tgf.tgf_measure(None, obs) == tgf.TGF_E_INVAL

@@ -284,6 +284,64 @@ def test_all_planes_twisted_plane_tiles(storage):
         compare(rows[:, 0], ref, storage, f"all planes twisted, variant {v}")
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32c12"])
+def test_block_shapes_per_extent(storage):
+    """The paper's mixed-L workload (Table A.1; the benchmark batch mixes
+    L = 6, 8, 10) with the LDS-staged kernel at the whole-plane work-group
+    shapes (252, 256, 200 sites) and at 256 sites for every L: each
+    configuration against the oracle; FP64 and FP32 full shapes give the same
+    bits (LDS or global memory, same arithmetic), and a configuration's result
+    does not depend on the batch around it."""
+    dims_list = [(6, 6, 18, 18), (8, 8, 24, 24), (10, 10, 30, 30)]
+    Us = [gen.near_identity(d, 0.3, seed=60 + k).numpy().copy() for k, d in enumerate(dims_list)]
+    refs = [oracle.flow(U.copy(), d, 0.02, 0.06, 0.02) for U, d in zip(Us, dims_list)]
+    names = tgf.variant_names()
+    out = {}
+    for shapes in ("planes", "256"):
+        f = tgf.Flow(dims_list, storage)
+        f.set_variant(names.index("site_lds_xcd"))
+        if shapes == "256":
+            for k in range(len(dims_list)):
+                f.set_block(k, 256)
+        say(f"  {storage} shapes {[f.block(k) for k in range(len(dims_list))]}")
+        f.load_all([torch.from_numpy(U).cuda() for U in Us])
+        rows = f.flow(0.02, 0.06, 0.02, 10)
+        for k, d in enumerate(dims_list):
+            compare(rows[:, k], refs[k], storage, f"shapes {shapes} {d}")
+        out[shapes] = rows
+    if storage != "f32c12":
+        assert np.array_equal(out["planes"], out["256"])
+    # batch = solo, bitwise, at the whole-plane shapes
+    for k, d in enumerate(dims_list):
+        g = tgf.Flow([d], storage)
+        g.set_variant(names.index("site_lds_xcd"))
+        g.load(0, torch.from_numpy(Us[k]).cuda())
+        solo = g.flow(0.02, 0.06, 0.02, 10)
+        assert np.array_equal(solo[:, 0], out["planes"][:, k]), d
+
+
+def test_autotune_per_extent(tmp_path):
+    """The autotuner keeps the LDS-staged kernel unless another is 2% faster,
+    and picks each extent class's work-group shape from {whole planes, 256}."""
+    dims_list = [(6, 6, 18, 18), (8, 8, 24, 24), (10, 10, 30, 30)]
+    Us = [torch.from_numpy(gen.near_identity(d, 0.3, seed=70 + k).numpy().copy()).cuda()
+          for k, d in enumerate(dims_list)]
+    f = tgf.Flow(dims_list * 2, "f32c12")
+    f.load_all(Us * 2)
+    cache = str(tmp_path / "tune.txt")
+    v = f.autotune(cache)
+    names = tgf.variant_names()
+    say(f"  autotune: {names[v]}, shapes {[f.block(k) for k in range(6)]}")
+    assert names[v].endswith("_xcd") and names[v] not in ("site_plq_xcd",)
+    for k in range(3):
+        assert f.block(k) == f.block(k + 3)
+        assert f.block(k) in ({252, 256}, {256}, {200, 256})[k]
+    g = tgf.Flow(dims_list * 2, "f32c12")
+    g.load_all(Us * 2)
+    assert g.autotune(cache) == v
+    assert [g.block(k) for k in range(6)] == [f.block(k) for k in range(6)]
+
+
 def test_resume_is_bitwise():
     U = torch.from_numpy(gen.near_identity(D1, 0.3, seed=14).numpy().copy()).cuda()
     a = tgf.Flow([D1], "f64")
