@@ -145,46 +145,45 @@ __global__ __launch_bounds__(256) void stage_site_kernel(StageArgs a) {
     site_lower_update<R, NE, 3>(W, Wout, X, c, g, acc[3], beps, ac, a);
 }
 
-// Site variant with su(3) force accumulators.  P_ah is linear and
-// P_ah(P^+) = -P_ah(P), so each upper plaquette Z^* P_{mu nu}(n) enters its two
-// links as +-P_ah in the 8-real form, taken from its two computed rows
-// (r2_proj_ah, no third row).  The four force accumulators take 4 x 8 reals
-// instead of 4 x 18.  Lower staples: FP32 forms each closed loop U_mu(n) x
-// staple in two rows and projects it the same way (fewer operations, no 3x3
-// sum, 188 instead of 240 registers); FP64 sums the three staples as 3x3
-// matrices and multiplies the sum by U_mu(n) once, which runs 1.5% faster at
-// its one wave per SIMD.
+// Site variant with su(3) force accumulators.  Each upper plaquette
+// Z^* P_{mu nu}(n) enters its two links with opposite signs (P_ah(P^+) =
+// -P_ah(P)) in the raw 8-real form (r2_raw: no third row, no per-term
+// projection); each link's sum is projected once (raw_to_alg).  Lower staples:
+// FP32 forms each closed loop U_mu(n) x staple in two rows and adds its raw
+// form the same way (fewer operations, no 3x3 sum, 188 instead of 240
+// registers); FP64 sums the three staples as 3x3 matrices and multiplies the
+// sum by U_mu(n) once, which runs 1.5% faster at its one wave per SIMD.
 template <class R, int NE, int MU, class LK>
 __device__ __forceinline__ void site_alg_update(const LK &W, gptr<v2<R>> Wout,
                                                 gptr<v2<R>> X, const CfgDesc &c, const Geo &g,
-                                                const Alg<R> &f, R beps, R ac,
+                                                const R f[8], R beps, R ac,
                                                 const StageArgs &a) {
     Alg<R> Z;
     if constexpr (sizeof(R) == 4) {
-        Z = f;
+        R k[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) k[t] = f[t];
 #pragma unroll
         for (int nu = 0; nu < 4; nu++) {
             if (nu == MU) continue;
             // U_mu(n) times the lower staple is the closed loop
             // U_mu(n) U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu), an SU(3) matrix
-            // times a cube root of unity: two rows, projected like the upper
-            // plaquettes
+            // times a cube root of unity: two rows, raw form
             const int imn = g.i + g.dn(nu);
             R2<R> P = r2_of(W.own(MU, g.i));
             P = r2_mul_nd(P, W(nu, imn + g.up(MU)));
             P = r2_mul_nd(P, W(MU, imn));
             P = r2_mul_nn(P, W(nu, imn));
-            const int k = twist_exp(c, MU, nu);
+            const int kt = twist_exp(c, MU, nu);
             // the loop is U_nu(n-nu)^+ P_{mu nu}(n-nu)^+ U_nu(n-nu): its factor is
             // Z_{mu nu}, the conjugate of the Z^* on the plaquette
-            if (k && g.n(MU) == 0 && g.back(nu) == 0) r2_scale(P, omega_pow<R>(k));
-            R A8[8];
-            r2_proj_ah(P, R(1), A8);
+            if (kt && g.n(MU) == 0 && g.back(nu) == 0) r2_scale(P, omega_pow<R>(kt));
+            R r[8];
+            r2_raw(P, r);
 #pragma unroll
-            for (int t = 0; t < 8; t++) Z.a[t] += A8[t];
+            for (int t = 0; t < 8; t++) k[t] += r[t];
         }
-#pragma unroll
-        for (int k = 0; k < 8; k++) Z.a[k] *= -beps;
+        Z = raw_to_alg(k, -beps);
     } else {
         M3<R> S;
         m_zero(S);
@@ -194,24 +193,25 @@ __device__ __forceinline__ void site_alg_update(const LK &W, gptr<v2<R>> Wout,
             acc_lower_staple(S, W, c, g, MU, nu);
         }
         const Alg<R> lo = proj_ah(mul_nn(W.own(MU, g.i), S), R(1));
+        Z = raw_to_alg(f, -beps);
 #pragma unroll
-        for (int k = 0; k < 8; k++) Z.a[k] = -beps * (f.a[k] + lo.a[k]);
+        for (int k = 0; k < 8; k++) Z.a[k] = fma(-beps, lo.a[k], Z.a[k]);
     }
     update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, reunit_now(a, c));
 }
 
-// The force of the four links of site g.i from su(3) accumulators, then the
-// four RK updates; W is the link accessor (global memory, or LDS-staged).
+// The force of the four links of site g.i from raw su(3) accumulators, then
+// the four RK updates; W is the link accessor (global memory, or LDS-staged).
 template <class R, int NE, class LK>
 __device__ __forceinline__ void site_alg_work(const LK &W, gptr<v2<R>> Wout, gptr<v2<R>> X,
                                               const CfgDesc &c, const Geo &g, R beps, R ac,
                                               const StageArgs &a) {
     const int i = g.i;
-    Alg<R> f[4];
+    R f[4][8];
 #pragma unroll
     for (int mu = 0; mu < 4; mu++)
 #pragma unroll
-        for (int k = 0; k < 8; k++) f[mu].a[k] = R(0);
+        for (int k = 0; k < 8; k++) f[mu][k] = R(0);
 #pragma unroll
     for (int mu = 0, p = 0; mu < 4; mu++)
 #pragma unroll
@@ -224,12 +224,12 @@ __device__ __forceinline__ void site_alg_work(const LK &W, gptr<v2<R>> Wout, gpt
             P = r2_mul_nd(P, W.own(nu, i));
             const int k = c.tw[p];
             if (k && g.n(mu) == 0 && g.n(nu) == 0) r2_scale(P, cconj(omega_pow<R>(k)));
-            R A8[8];
-            r2_proj_ah(P, R(1), A8);
+            R r[8];
+            r2_raw(P, r);
 #pragma unroll
             for (int t = 0; t < 8; t++) {
-                f[mu].a[t] += A8[t];
-                f[nu].a[t] -= A8[t];
+                f[mu][t] += r[t];
+                f[nu][t] -= r[t];
             }
         }
     site_alg_update<R, NE, 0>(W, Wout, X, c, g, f[0], beps, ac, a);
@@ -241,9 +241,11 @@ __device__ __forceinline__ void site_alg_work(const LK &W, gptr<v2<R>> Wout, gpt
 // The lower terms of link MU not yet taken from the wave, then the update.
 template <class R, int NE, int MU, class LK>
 __device__ __forceinline__ void wave_update(const LK &W, gptr<v2<R>> Wout, gptr<v2<R>> X,
-                                            const CfgDesc &c, const Geo &g, const Alg<R> &f,
+                                            const CfgDesc &c, const Geo &g, const R f[8],
                                             R beps, R ac, const StageArgs &a, unsigned done) {
-    Alg<R> Z = f;
+    R k[8];
+#pragma unroll
+    for (int t = 0; t < 8; t++) k[t] = f[t];
 #pragma unroll
     for (int nu = 0; nu < 4; nu++) {
         if (nu == MU || ((done >> (4 * MU + nu)) & 1u)) continue;
@@ -252,27 +254,27 @@ __device__ __forceinline__ void wave_update(const LK &W, gptr<v2<R>> Wout, gptr<
         P = r2_mul_nd(P, W(nu, imn + g.up(MU)));
         P = r2_mul_nd(P, W(MU, imn));
         P = r2_mul_nn(P, W(nu, imn));
-        const int k = twist_exp(c, MU, nu);
-        if (k && g.n(MU) == 0 && g.back(nu) == 0) r2_scale(P, omega_pow<R>(k));
-        R A8[8];
-        r2_proj_ah(P, R(1), A8);
+        const int kt = twist_exp(c, MU, nu);
+        if (kt && g.n(MU) == 0 && g.back(nu) == 0) r2_scale(P, omega_pow<R>(kt));
+        R r[8];
+        r2_raw(P, r);
 #pragma unroll
-        for (int t = 0; t < 8; t++) Z.a[t] += A8[t];
+        for (int t = 0; t < 8; t++) k[t] += r[t];
     }
-#pragma unroll
-    for (int t = 0; t < 8; t++) Z.a[t] *= -beps;
-    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, Z, ac, a.stage, reunit_now(a, c));
+    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, raw_to_alg(k, -beps), ac, a.stage,
+                         reunit_now(a, c));
 }
 
 // site_alg_work with in-wave plaquette reuse (FP32): a lane's lower staple
-// term of link mu in plane nu is the conjugated plaquette algebra of site
-// n - nu; when that site lies in the same wave for every active lane (the
-// (n0, n1) directions when a 64-site tile holds whole planes), its A is
-// pulled from that lane right after it is formed, and conjugated by one link:
-//   link mu < nu: -U_nu(n-nu)^+ A_{mu nu}(n-nu) U_nu(n-nu),
-//   link nu > mu: +U_mu(n-mu)^+ A_{mu nu}(n-mu) U_mu(n-mu).
+// term of link mu in plane nu is the conjugated plaquette of site n - nu;
+// when that site lies in the same wave for every active lane (the (n0, n1)
+// directions when a 64-site wave holds whole planes), its raw form is pulled
+// from that lane right after it is formed, and conjugated by one link:
+//   link mu < nu: -U_nu(n-nu)^+ [Z^*P_{mu nu}](n-nu) U_nu(n-nu),
+//   link nu > mu: +U_mu(n-mu)^+ [Z^*P_{mu nu}](n-mu) U_mu(n-mu)   (raw forms).
 // Other lower terms are formed directly.  The choice depends only on the
-// tile, so a configuration's result does not depend on the batch around it.
+// work-group shape of the configuration, so a configuration's result does not
+// depend on the batch around it.
 template <class R, int NE, class LK>
 __device__ __forceinline__ void site_wave_work(const LK &W, gptr<v2<R>> Wout, gptr<v2<R>> X,
                                                const CfgDesc &c, const Geo &g, R beps, R ac,
@@ -280,11 +282,11 @@ __device__ __forceinline__ void site_wave_work(const LK &W, gptr<v2<R>> Wout, gp
     // nw: active lanes of this wave, holding sites tb .. tb + nw - 1
     const int i = g.i;
     const int tb = i - (int)(threadIdx.x & 63);        // first site of this wave
-    Alg<R> f[4];
+    R f[4][8];
 #pragma unroll
     for (int mu = 0; mu < 4; mu++)
 #pragma unroll
-        for (int k = 0; k < 8; k++) f[mu].a[k] = R(0);
+        for (int k = 0; k < 8; k++) f[mu][k] = R(0);
     unsigned done = 0;                                  // bit 4 mu + nu: lower term (mu, nu)
 #pragma unroll
     for (int mu = 0, p = 0; mu < 4; mu++)
@@ -296,31 +298,31 @@ __device__ __forceinline__ void site_wave_work(const LK &W, gptr<v2<R>> Wout, gp
             P = r2_mul_nd(P, W.own(nu, i));
             const int k = c.tw[p];
             if (k && g.n(mu) == 0 && g.n(nu) == 0) r2_scale(P, cconj(omega_pow<R>(k)));
-            R A8[8];
-            r2_proj_ah(P, R(1), A8);
+            R r[8];
+            r2_raw(P, r);
 #pragma unroll
             for (int t = 0; t < 8; t++) {
-                f[mu].a[t] += A8[t];
-                f[nu].a[t] -= A8[t];
+                f[mu][t] += r[t];
+                f[nu][t] -= r[t];
             }
             const int imn = i + g.dn(nu);
             if (__all((unsigned)(imn - tb) < (unsigned)nw)) {
                 R an[8], cc[8];
 #pragma unroll
-                for (int t = 0; t < 8; t++) an[t] = __shfl(A8[t], imn - tb);
-                conj_alg(W(nu, imn), an, cc);
+                for (int t = 0; t < 8; t++) an[t] = __shfl(r[t], imn - tb);
+                conj_raw(W(nu, imn), an, cc);
 #pragma unroll
-                for (int t = 0; t < 8; t++) f[mu].a[t] -= cc[t];
+                for (int t = 0; t < 8; t++) f[mu][t] -= cc[t];
                 done |= 1u << (4 * mu + nu);
             }
             const int imm = i + g.dn(mu);
             if (__all((unsigned)(imm - tb) < (unsigned)nw)) {
                 R an[8], cc[8];
 #pragma unroll
-                for (int t = 0; t < 8; t++) an[t] = __shfl(A8[t], imm - tb);
-                conj_alg(W(mu, imm), an, cc);
+                for (int t = 0; t < 8; t++) an[t] = __shfl(r[t], imm - tb);
+                conj_raw(W(mu, imm), an, cc);
 #pragma unroll
-                for (int t = 0; t < 8; t++) f[nu].a[t] += cc[t];
+                for (int t = 0; t < 8; t++) f[nu][t] += cc[t];
                 done |= 1u << (4 * nu + mu);
             }
         }

@@ -176,17 +176,24 @@ __device__ __forceinline__ void m_acc_scaled_dag(M3<R> &acc, cx<R> z, const M3<R
         for (int j = 0; j < 3; j++) acc.e[i][j] = cmadd_cc(acc.e[i][j], z, A.e[j][i]);
 }
 
+// conj(aj bk - ak bj), one entry of a conjugated cross product, as one
+// multiply and three fused multiply-adds per real part (the form with two
+// complex products and a subtraction takes five).
+template <class R>
+__device__ __forceinline__ cx<R> cross_conj(cx<R> aj, cx<R> bk, cx<R> ak, cx<R> bj) {
+    const R re = fma(aj.x, bk.x, fma(-aj.y, bk.y, fma(-ak.x, bj.x, ak.y * bj.y)));
+    const R im = fma(-aj.x, bk.y, fma(-aj.y, bk.x, fma(ak.x, bj.y, ak.y * bj.x)));
+    return {re, im};
+}
+
 // Third row of an SU(3) matrix from the first two: row2 = conj(row0 x row1).
 template <class R>
 __device__ __forceinline__ void rebuild_row2(M3<R> &U) {
     const cx<R> *a = U.e[0], *b = U.e[1];
-    // (a x b)_0 = a1 b2 - a2 b1, etc.; then conjugate
-    cx<R> c0 = csub(cmul(a[1], b[2]), cmul(a[2], b[1]));
-    cx<R> c1 = csub(cmul(a[2], b[0]), cmul(a[0], b[2]));
-    cx<R> c2 = csub(cmul(a[0], b[1]), cmul(a[1], b[0]));
-    U.e[2][0] = cconj(c0);
-    U.e[2][1] = cconj(c1);
-    U.e[2][2] = cconj(c2);
+    // (a x b)_0 = a1 b2 - a2 b1, (a x b)_1 = a2 b0 - a0 b2, (a x b)_2 = a0 b1 - a1 b0
+    U.e[2][0] = cross_conj(a[1], b[2], a[2], b[1]);
+    U.e[2][1] = cross_conj(a[2], b[0], a[0], b[2]);
+    U.e[2][2] = cross_conj(a[0], b[1], a[1], b[0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -292,10 +299,10 @@ __device__ __forceinline__ R2<R> r2_of(const M3<R> &A) {
 template <class R>
 __device__ __forceinline__ void r2_proj_ah(const R2<R> &P, R s, R out[8]) {
     const cx<R> *a = P.e[0], *b = P.e[1];
-    cx<R> p20 = cconj(csub(cmul(a[1], b[2]), cmul(a[2], b[1])));
-    cx<R> p21 = cconj(csub(cmul(a[2], b[0]), cmul(a[0], b[2])));
+    cx<R> p20 = cross_conj(a[1], b[2], a[2], b[1]);
+    cx<R> p21 = cross_conj(a[2], b[0], a[0], b[2]);
     // Im P22 = -Im(a0 b1 - a1 b0)
-    R im22 = -((a[0].x * b[1].y + a[0].y * b[1].x) - (a[1].x * b[0].y + a[1].y * b[0].x));
+    R im22 = fma(-a[0].x, b[1].y, fma(-a[0].y, b[1].x, fma(a[1].x, b[0].y, a[1].y * b[0].x)));
     R h = R(0.5) * s;
     out[0] = h * (a[1].x - b[0].x);
     out[1] = h * (a[1].y + b[0].y);
@@ -306,6 +313,96 @@ __device__ __forceinline__ void r2_proj_ah(const R2<R> &P, R s, R out[8]) {
     R tr3 = (a[0].y + b[1].y + im22) * R(1.0 / 3.0);
     out[6] = s * (a[0].y - tr3);
     out[7] = s * (b[1].y - tr3);
+}
+
+// ---------------------------------------------------------------------------
+// Raw anti-Hermitian form (8 reals) of the force terms.  For a matrix M,
+//   k[0..5] = z01, z02, z12 with z_ij = M_ij - conj(M_ji)   (complex pairs),
+//   k[6] = u = Im M_00 - Im M_22,   k[7] = v = Im M_11 - Im M_22,
+// so that
+//   P_ah(M) = { z_ij / 2 ;  diagonal i (2u - v)/3, i (2v - u)/3, -(sum) }.
+// The form is linear in M and odd under M -> M^+, and the traceless part of
+// M - M^+ is what conjugation by a unitary U acts on (conj_raw), so force
+// terms are summed in it and halved and projected once per link
+// (raw_to_alg) instead of once per term.
+
+// Raw form of P in SU(3) (times a cube root of unity) given by rows 0, 1: the
+// row-2 entries enter through row2 = conj(row0 x row1):
+//   z02 = P02 - conj(P20) = a2 - (a1 b2 - a2 b1),
+//   z12 = P12 - conj(P21) = b2 - (a2 b0 - a0 b2),
+//   Im P22 = -Im(a0 b1 - a1 b0).
+template <class R>
+__device__ __forceinline__ void r2_raw(const R2<R> &P, R k[8]) {
+    const cx<R> *a = P.e[0], *b = P.e[1];
+    k[0] = a[1].x - b[0].x;
+    k[1] = a[1].y + b[0].y;
+    k[2] = fma(-a[1].x, b[2].x, fma(a[1].y, b[2].y, fma(a[2].x, b[1].x, fma(-a[2].y, b[1].y, a[2].x))));
+    k[3] = fma(-a[1].x, b[2].y, fma(-a[1].y, b[2].x, fma(a[2].x, b[1].y, fma(a[2].y, b[1].x, a[2].y))));
+    k[4] = fma(-a[2].x, b[0].x, fma(a[2].y, b[0].y, fma(a[0].x, b[2].x, fma(-a[0].y, b[2].y, b[2].x))));
+    k[5] = fma(-a[2].x, b[0].y, fma(-a[2].y, b[0].x, fma(a[0].x, b[2].y, fma(a[0].y, b[2].x, b[2].y))));
+    const R im22 = fma(-a[0].x, b[1].y, fma(-a[0].y, b[1].x, fma(a[1].x, b[0].y, a[1].y * b[0].x)));
+    k[6] = a[0].y - im22;
+    k[7] = b[1].y - im22;
+}
+
+// s * P_ah(M) in the 8-real su(3) form from the raw form of M.
+template <class R>
+__device__ __forceinline__ Alg<R> raw_to_alg(const R k[8], R s) {
+    Alg<R> X;
+    const R h = R(0.5) * s, t = s * R(1.0 / 3.0);
+#pragma unroll
+    for (int j = 0; j < 6; j++) X.a[j] = h * k[j];
+    X.a[6] = t * fma(R(2), k[6], -k[7]);
+    X.a[7] = t * fma(R(2), k[7], -k[6]);
+    return X;
+}
+
+// Raw form of U^+ M U from the raw form k of M: with T the traceless part of
+// M - M^+ (off-diagonals z_ij, diagonal 2i (2u - v)/3, 2i (2v - u)/3, ...),
+// B = T U, C = U^+ B (upper off-diagonals and the first two diagonal entries;
+// C is traceless, so Im C_22 = -(Im C_00 + Im C_11)).
+template <class R>
+__device__ __forceinline__ void conj_raw(const M3<R> &U, const R k[8], R c[8]) {
+    const cx<R> x01 = {k[0], k[1]}, x02 = {k[2], k[3]}, x12 = {k[4], k[5]};
+    const R w = R(2.0 / 3.0);
+    const R d0 = w * fma(R(2), k[6], -k[7]), d1 = w * fma(R(2), k[7], -k[6]);
+    const R d2 = -(d0 + d1);
+    M3<R> B;
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        cx<R> t = {-d0 * U.e[0][j].y, d0 * U.e[0][j].x};
+        t = cmadd(t, x01, U.e[1][j]);
+        t = cmadd(t, x02, U.e[2][j]);
+        B.e[0][j] = t;
+        t = {-d1 * U.e[1][j].y, d1 * U.e[1][j].x};
+        t = cmadd(t, cx<R>{-x01.x, x01.y}, U.e[0][j]);
+        t = cmadd(t, x12, U.e[2][j]);
+        B.e[1][j] = t;
+        t = {-d2 * U.e[2][j].y, d2 * U.e[2][j].x};
+        t = cmadd(t, cx<R>{-x02.x, x02.y}, U.e[0][j]);
+        t = cmadd(t, cx<R>{-x12.x, x12.y}, U.e[1][j]);
+        B.e[2][j] = t;
+    }
+    const int ia[3] = {0, 0, 1}, ib[3] = {1, 2, 2};
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+        cx<R> s = {R(0), R(0)};
+#pragma unroll
+        for (int m = 0; m < 3; m++) s = cmadd_cn(s, U.e[m][ia[t]], B.e[m][ib[t]]);
+        c[2 * t] = s.x;
+        c[2 * t + 1] = s.y;
+    }
+    R im[2];
+#pragma unroll
+    for (int d = 0; d < 2; d++) {
+        R v = 0;
+#pragma unroll
+        for (int m = 0; m < 3; m++) v = fma(U.e[m][d].x, B.e[m][d].y, fma(-U.e[m][d].y, B.e[m][d].x, v));
+        im[d] = v;
+    }
+    // u' = (Im C00 - Im C22)/2 = Im C00 + Im C11 / 2, v' = Im C11 + Im C00 / 2
+    c[6] = fma(R(0.5), im[1], im[0]);
+    c[7] = fma(R(0.5), im[0], im[1]);
 }
 
 // C = U^+ A U for A in su(3) (8-real form); the result is again in su(3).
