@@ -31,8 +31,13 @@ sys.path.insert(0, ROOT)
 METRIC = "flowed site-updates/s + HBM GB/s (FP32 batched vs FP64 plain) at t^2E err<=1e-5"
 EPS = 0.01
 HBM_PEAK_GBS = 8000.0
-# Non-packed FP32 (and FP64) vector peak: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz
+# Published MI355X vector peaks (TFLOP/s): FP32 157.3 (with packed FP32), FP64 78.6.
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+# Non-packed FMA issue: 256 CU x 64 lanes x 2 flop x 2.4 GHz.  The build turns
+# packed FP32 off, so this is what the FP32 kernels can issue at most.
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+LARGE_STEPS = 100
 
 
 def host_cpu():
@@ -62,8 +67,11 @@ def batch_workload():
     return cfgs
 
 
-def large_workload():
-    return [((32, 32, 96, 96), None, 5, 0.09 * 32 * 32 / 8)]
+def large_workload(steps=None):
+    """One 32x32x96x96 Haar box flowed to c = 0.3 (t_end 11.52), or only the
+    first `steps` steps of that flow."""
+    t_end = 0.09 * 32 * 32 / 8 if steps is None else steps * EPS
+    return [((32, 32, 96, 96), None, 5, t_end)]
 
 
 def n_steps(t_end, t0=0.0):
@@ -182,39 +190,34 @@ def time_flows(tgf, torch, cfgs, inputs, storage, steps, warmup, flags=0, reunit
     return f, rows, dt
 
 
-def cpu_baseline(cfgs, inputs, gpu_rows, target_s=12.0):
+def cpu_baseline(cfgs, inputs, gpu_rows, target_s=12.0, single_s=6.0):
     """The FP64 oracle on a bounded sample of the same workload: whole flows of
     the first configurations of the batch (each from t = 0 to its t_end with
-    rows only at t_end), as many as fit in about target_s; the sample's t^2 E
-    at t_end is also compared with the GPU rows of the timed run."""
+    rows only at t_end) on all host threads, as many as fit in about
+    target_s, and the first steps of configuration 0 on one thread (about
+    single_s); the sample's t^2 E at t_end is also compared with the GPU rows
+    of the timed run."""
     import numpy as np
 
     import oracle
     oracle.build(force=False)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    oracle.set_threads(threads)
-    # probe one step of config 0: if its whole flow does not fit the budget,
-    # the sample is the first steps of that flow instead
+    # one thread: steps of config 0 until about single_s
     dims0 = cfgs[0][0]
     V0 = int(np.prod(dims0))
+    oracle.set_threads(1)
     U = inputs[0].cpu().numpy().copy()
     t = time.perf_counter()
     oracle.rk3_step(U, dims0, EPS)
-    rate = V0 / (time.perf_counter() - t)
-    if V0 * n_steps(cfgs[0][3]) / rate > target_s:
-        nst = max(1, int(target_s * rate / V0))
-        U = inputs[0].cpu().numpy().copy()
-        t = time.perf_counter()
-        oracle.flow(U, dims0, EPS, nst * EPS, 0.0)
-        dt = time.perf_counter() - t
-        return {
-            "value": V0 * nst / dt,
-            "unit": "site-updates/s",
-            "cores": oracle.get_threads(), "host_cpu": host_cpu(),
-            "kind": "oracle",
-            "sample": f"config 0 ({'x'.join(map(str, dims0))}), first {nst} FP64 RK3 steps of "
-                      f"eps={EPS} and one measurement: {V0 * nst} site-updates in {dt:.1f} s",
-        }, None, 1
+    n1 = max(1, int(single_s / (time.perf_counter() - t)))
+    U = inputs[0].cpu().numpy().copy()
+    t = time.perf_counter()
+    oracle.flow(U, dims0, EPS, n1 * EPS, 0.0)
+    dt1 = time.perf_counter() - t
+    single = {"value": V0 * n1 / dt1, "unit": "site-updates/s", "cores": 1,
+              "sample": f"config 0 ({'x'.join(map(str, dims0))}), first {n1} FP64 RK3 steps: "
+                        f"{V0 * n1} site-updates in {dt1:.1f} s"}
+    oracle.set_threads(threads)
     done, su, elapsed, errs = 0, 0, 0.0, []
     while done < len(cfgs) and (done == 0 or elapsed * (done + 1) / done <= target_s):
         dims, _, _, t_end = cfgs[done]
@@ -232,11 +235,12 @@ def cpu_baseline(cfgs, inputs, gpu_rows, target_s=12.0):
     return {
         "value": su / elapsed,
         "unit": "site-updates/s",
-        "cores": oracle.get_threads(), "host_cpu": host_cpu(),
+        "cores": oracle.get_threads(), "host_cpu": host_cpu(), "host_nproc": os.cpu_count(),
         "kind": "oracle",
         "sample": f"configs 0..{done - 1} of the batch ({', '.join(shapes)}), whole FP64 flows "
                   f"with eps={EPS} from t=0 to t_end and one measurement each: {su} site-updates "
                   f"in {elapsed:.1f} s",
+        "single_thread": single,
     }, (max(errs) if errs else None), done
 
 
@@ -449,6 +453,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mc", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--large-steps", type=int, default=LARGE_STEPS)
     ap.add_argument("--mc-reps", type=int, default=3)
     ap.add_argument("--mode", choices=("flow", "copy", "mc", "sun"), default="flow",
                     help="copy: time the library's plain HBM copy kernel (counter calibration); "
@@ -479,6 +485,7 @@ def main():
         return
 
     cfgs = batch_workload() if args.workload == "batch" else large_workload()
+    args.no_large = args.no_large or args.workload != "batch"
     log(f"generating {len(cfgs)} configurations on the GPU")
     inputs = make_inputs(cfgs, "cuda")
     torch.cuda.synchronize()
@@ -495,57 +502,8 @@ def main():
                              variant=args.variant)
     variant = tgf.variant_names()[f.variant]
     value = site_updates / dt
-
-    # kernel durations with HIP events on the library's stream (same launches)
     log("kernel timing pass")
-    f.load_all(inputs)
-    f.flow(EPS, [c[3] for c in cfgs], 0.1, 10, tgf.TGF_TIMING)
-    tm = f.timing()
-    n_launch = tm["stage_launches"]
-    stage_avg_ms = tm["stage_ms"] / n_launch
-    bytes_per_launch = tm["stage_bytes"] / n_launch
-    site_stages_per_launch = 3 * tm["stage_site_updates"] / n_launch
-    flops_per_launch = site_stages_per_launch * flops_per_site_stage(args.storage, variant)
-    gbs = bytes_per_launch / (stage_avg_ms * 1e-3) / 1e9
-    tflops = flops_per_launch / (stage_avg_ms * 1e-3) / 1e12
-    hbm_frac = gbs / HBM_PEAK_GBS
-    alu_frac = tflops / ALU_PEAK_TFLOPS
-    alu = alu_frac >= hbm_frac
-    traffic, traffic_src = profiled_traffic(variant, args.storage, args.workload)
-    if variant.startswith("site_alg3"):
-        kname = "stage_site_alg3_kernel"
-    elif variant.startswith("site_lds"):
-        kname = "stage_site_lds_kernel"
-    elif variant.startswith("site_plq"):
-        kname = "stage_site_plq_kernel"
-    elif variant.startswith("site_alg"):
-        # FP32 runs the two-waves-per-SIMD build of the same kernel
-        kname = "stage_site_alg_kernel" if args.storage == "f64" else "stage_site_alg2_kernel"
-    else:
-        kname = {"site": "stage_site_kernel", "link": "stage_link_kernel"}[variant.split("_")[0]]
-    targ = "double, 9" if args.storage == "f64" else ("float, 6" if args.storage == "f32c12"
-                                                      else "float, 9")
-    roofline = {
-        "kernel": f"{kname}<{targ}>",
-        "bound": "alu" if alu else "hbm",
-        "achieved": round(tflops if alu else gbs, 3),
-        "peak": round(ALU_PEAK_TFLOPS, 1) if alu else HBM_PEAK_GBS,
-        "unit": "TFLOP/s" if alu else "GB/s",
-        "frac": round(alu_frac if alu else hbm_frac, 4),
-        "traffic": traffic,
-        "traffic_source": traffic_src,
-        "alu_tflops": round(tflops, 2),
-        "alu_frac": round(alu_frac, 4),
-        "hbm_gbs_algorithmic": round(gbs, 1),
-        "hbm_frac": round(hbm_frac, 4),
-        "avg_launch_ms": round(stage_avg_ms, 4),
-        "launches": int(n_launch),
-        "bytes_per_launch": round(bytes_per_launch),
-        "flops_per_launch": round(flops_per_launch),
-        "bytes_per_site_step": bytes_per_site_step(args.storage, variant),
-        "flops_per_site_step": round(flops_per_site_step(args.storage, variant)),
-        "measure_ms_per_flow": round(tm["measure_ms"], 3),
-    }
+    roofline = stage_roofline(tgf, f, cfgs, inputs, args.storage, variant, args.workload)
     whole_gbs = site_updates * bytes_per_site_step(args.storage, variant) / dt / 1e9
 
     out = {
@@ -574,6 +532,7 @@ def main():
             "meas_dt": 0.1,
             "reunit_every": 10,
             "variant": variant,
+            "lds_block_sites": block_shapes(f, cfgs),
             "hip_graph": True,
         },
         "roofline": roofline,
@@ -591,10 +550,16 @@ def main():
         rel = np.abs(rows[:, :, 2] - rows64[:, :, 2])[pos] / np.abs(rows64[:, :, 2][pos])
         out["fp64_plain"] = {"value": round(site_updates / dt64, 1), "unit": "site-updates/s",
                              "ms_per_step": round(dt64 * 1e3, 3), "steps": k64,
-                             "variant": tgf.variant_names()[f64.variant]}
+                             "variant": tgf.variant_names()[f64.variant],
+                             "lds_block_sites": block_shapes(f64, cfgs)}
         out["speedup_vs_fp64_plain"] = round(dt64 / dt, 3)
         out["t2E_max_rel_err_vs_fp64_gpu"] = float(rel.max())
         del f64
+        torch.cuda.empty_cache()
+
+    if args.workload == "batch" and not args.no_large:
+        log(f"large box: first {args.large_steps} steps of 32x32x96x96, FP32 12-real and FP64")
+        out["large"] = large_leg(tgf, torch, np, args.large_steps)
 
     if not args.no_mc:
         log("timing the Monte Carlo on the same geometry")
@@ -607,6 +572,100 @@ def main():
         out["t2E_max_rel_err_vs_oracle_sample"] = err
         out["oracle_sample_configs"] = n_sample
     print(json.dumps(out), flush=True)
+
+
+def block_shapes(f, cfgs):
+    """LDS work-group sites per configuration extent, {"6x6x18x18": 252, ...}."""
+    return {"x".join(map(str, c[0])): f.block(k) for k, c in enumerate(cfgs)}
+
+
+def kernel_name(variant, storage):
+    if variant.startswith("site_alg3"):
+        kname = "stage_site_alg3_kernel"
+    elif variant.startswith("site_lds"):
+        kname = "stage_site_lds_kernel"
+    elif variant.startswith("site_plq"):
+        kname = "stage_site_plq_kernel"
+    elif variant.startswith("site_alg"):
+        # FP32 runs the two-waves-per-SIMD build of the same kernel
+        kname = "stage_site_alg_kernel" if storage == "f64" else "stage_site_alg2_kernel"
+    else:
+        kname = {"site": "stage_site_kernel", "link": "stage_link_kernel"}[variant.split("_")[0]]
+    targ = "double, 9" if storage == "f64" else ("float, 6" if storage == "f32c12" else "float, 9")
+    return f"{kname}<{targ}>"
+
+
+def stage_roofline(tgf, f, cfgs, inputs, storage, variant, workload):
+    """The stage kernel's roofline from one flow with HIP events on the
+    library's stream around every launch: algorithmic bytes per launch / its
+    average duration against the 8 TB/s HBM peak (the bound of the metric),
+    and the modelled flops against the published vector peak."""
+    f.load_all(inputs)
+    f.flow(EPS, [c[3] for c in cfgs], 0.1, 10, tgf.TGF_TIMING)
+    tm = f.timing()
+    n_launch = tm["stage_launches"]
+    stage_avg_ms = tm["stage_ms"] / n_launch
+    bytes_per_launch = tm["stage_bytes"] / n_launch
+    site_stages_per_launch = 3 * tm["stage_site_updates"] / n_launch
+    flops_per_launch = site_stages_per_launch * flops_per_site_stage(storage, variant)
+    gbs = bytes_per_launch / (stage_avg_ms * 1e-3) / 1e9
+    tflops = flops_per_launch / (stage_avg_ms * 1e-3) / 1e12
+    traffic, traffic_src = profiled_traffic(variant, storage, workload)
+    pub = FP64_PEAK_TFLOPS if storage == "f64" else FP32_PEAK_TFLOPS
+    return {
+        "kernel": kernel_name(variant, storage),
+        "bound": "hbm",
+        "achieved": round(gbs, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(gbs / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "traffic_source": traffic_src,
+        "avg_launch_ms": round(stage_avg_ms, 4),
+        "launches": int(n_launch),
+        "bytes_per_launch": round(bytes_per_launch),
+        "bytes_per_site_step": bytes_per_site_step(storage, variant),
+        "alu_model": {
+            "flops_per_site_step": round(flops_per_site_step(storage, variant)),
+            "flops_per_launch": round(flops_per_launch),
+            "tflops": round(tflops, 2),
+            "peak_published": pub,
+            "frac_of_published": round(tflops / pub, 4),
+            "peak_nonpacked_issue": round(ALU_PEAK_TFLOPS, 1),
+            "frac_of_nonpacked_issue": round(tflops / ALU_PEAK_TFLOPS, 4),
+        },
+        "measure_ms_per_flow": round(tm["measure_ms"], 3),
+    }
+
+
+def large_leg(tgf, torch, np, steps):
+    """The first `steps` RK3 steps of the 32x32x96x96 Haar box (9.4M sites),
+    measured every 0.1: FP32 12-real (the default kernel) and FP64 plain, whole
+    flow wall time (graph) and the stage kernel's roofline, and the t^2 E
+    error of FP32 against FP64 at every row."""
+    cfgs = large_workload(steps)
+    inputs = make_inputs(cfgs, "cuda")
+    torch.cuda.synchronize()
+    su = sum(math.prod(c[0]) * n_steps(c[3]) for c in cfgs)
+    out = {"workload": f"32x32x96x96 Haar (seed 5), twist n01=1, first {steps} RK3 steps of "
+                       f"eps={EPS} (t = {steps * EPS:g}), rows every 0.1",
+           "site_updates_per_flow": su}
+    rows = {}
+    for storage in ("f32c12", "f64"):
+        f, r, dt = time_flows(tgf, torch, cfgs, inputs, storage, 2, 1)
+        variant = tgf.variant_names()[f.variant]
+        out[storage] = {"value": round(su / dt, 1), "unit": "site-updates/s",
+                        "ms_per_flow": round(dt * 1e3, 2), "variant": variant,
+                        "roofline": stage_roofline(tgf, f, cfgs, inputs, storage, variant,
+                                                   "large")}
+        rows[storage] = r
+        del f
+        torch.cuda.empty_cache()
+    out["speedup_vs_fp64_plain"] = round(out["f32c12"]["value"] / out["f64"]["value"], 3)
+    pos = rows["f64"][:, 0, 0] > 0
+    rel = np.abs(rows["f32c12"][pos, 0, 2] - rows["f64"][pos, 0, 2]) / np.abs(rows["f64"][pos, 0, 2])
+    out["t2E_max_rel_err_f32_vs_f64"] = float(rel.max())
+    return out
 
 
 if __name__ == "__main__":
