@@ -69,6 +69,15 @@ struct Layout {
 
 int ne_of(tgf_storage st) { return st == TGF_F32_C12 ? 6 : 9; }
 
+// A storage argument from a C caller may hold any int; it is read as its raw
+// value (not as the C++ enum, whose out-of-range values are undefined) and
+// only then trusted as a tgf_storage.
+bool storage_ok(const tgf_storage &st) {
+    int v;
+    memcpy(&v, &st, sizeof v);
+    return v >= (int)TGF_F64_FULL && v <= (int)TGF_F32_C12;
+}
+
 // Sites per work-group of the LDS-staged stage variants: whole (n0, n1) planes
 // (so that every neighbour in directions 0 and 1 lies in the block) when at
 // least two of them fill half of the 256 threads; otherwise 256.  For the
@@ -442,14 +451,14 @@ extern "C" {
 const char *tgf_last_error(void) { return g_err.c_str(); }
 
 size_t tgf_workspace_bytes(int32_t n_cfg, const tgf_geom *geoms, tgf_storage st) {
-    if (st < TGF_F64_FULL || st > TGF_F32_C12) return 0;
+    if (!storage_ok(st)) return 0;
     if (validate_geoms(n_cfg, geoms) != TGF_OK) return 0;
     return make_layout(n_cfg, geoms, st).total;
 }
 
 size_t tgf_workspace_bytes_sun(int32_t nc, int32_t n_cfg, const tgf_geom *geoms,
                                tgf_storage st) {
-    if (nc < 2 || nc > 8 || st != TGF_F64_FULL) return 0;
+    if (nc < 2 || nc > 8 || !storage_ok(st) || st != TGF_F64_FULL) return 0;
     if (validate_geoms(n_cfg, geoms, nc, true) != TGF_OK) return 0;
     return make_layout(n_cfg, geoms, st, nc, true).total;
 }
@@ -460,7 +469,7 @@ static tgf_status create_impl(tgf_ctx **out, int nc, bool general, int32_t n_cfg
     g_err.clear();
     if (!out) return fail(TGF_E_INVAL, "out is NULL");
     *out = nullptr;
-    if (st < TGF_F64_FULL || st > TGF_F32_C12) return fail(TGF_E_INVAL, "unknown storage");
+    if (!storage_ok(st)) return fail(TGF_E_INVAL, "unknown storage");
     if (general && (nc < 2 || nc > 8)) return fail(TGF_E_INVAL, "nc must be 2..8");
     if (general && st != TGF_F64_FULL)
         return fail(TGF_E_UNSUPPORTED, "SU(N) contexts use TGF_F64_FULL storage");
