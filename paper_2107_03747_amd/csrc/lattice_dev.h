@@ -95,27 +95,27 @@ struct Geo {
     int s1, s2, s3;       // index strides (s0 = 1)
     int n0, n1, n2, n3;   // coordinates of this site
     int i;                // site index
-    __device__ __forceinline__ int d(int mu) const {
+    __host__ __device__ __forceinline__ int d(int mu) const {
         return mu == 0 ? d0 : (mu == 1 ? d1 : (mu == 2 ? d2 : d3));
     }
-    __device__ __forceinline__ int s(int mu) const {
+    __host__ __device__ __forceinline__ int s(int mu) const {
         return mu == 0 ? 1 : (mu == 1 ? s1 : (mu == 2 ? s2 : s3));
     }
-    __device__ __forceinline__ int n(int mu) const {
+    __host__ __device__ __forceinline__ int n(int mu) const {
         return mu == 0 ? n0 : (mu == 1 ? n1 : (mu == 2 ? n2 : n3));
     }
-    __device__ __forceinline__ int up(int mu) const {        // delta to n + mu
+    __host__ __device__ __forceinline__ int up(int mu) const {        // delta to n + mu
         return n(mu) == d(mu) - 1 ? -(d(mu) - 1) * s(mu) : s(mu);
     }
-    __device__ __forceinline__ int dn(int mu) const {        // delta to n - mu
+    __host__ __device__ __forceinline__ int dn(int mu) const {        // delta to n - mu
         return n(mu) == 0 ? (d(mu) - 1) * s(mu) : -s(mu);
     }
-    __device__ __forceinline__ int back(int mu) const {      // coordinate n_mu - 1 (periodic)
+    __host__ __device__ __forceinline__ int back(int mu) const {      // coordinate n_mu - 1 (periodic)
         return n(mu) == 0 ? d(mu) - 1 : n(mu) - 1;
     }
 };
 
-__device__ __forceinline__ Geo make_geo(const CfgDesc &c, int i) {
+__host__ __device__ __forceinline__ Geo make_geo(const CfgDesc &c, int i) {
     Geo g;
     g.i = i;
     g.d0 = c.d[0]; g.d1 = c.d[1]; g.d2 = c.d[2]; g.d3 = c.d[3];
@@ -130,7 +130,7 @@ __device__ __forceinline__ Geo make_geo(const CfgDesc &c, int i) {
     return g;
 }
 
-__device__ __forceinline__ int plane_index(int mu, int nu) {
+__host__ __device__ __forceinline__ int plane_index(int mu, int nu) {
     // (0,1)->0 (0,2)->1 (0,3)->2 (1,2)->3 (1,3)->4 (2,3)->5, mu < nu
     return mu == 0 ? nu - 1 : (mu == 1 ? nu + 1 : 5);
 }
@@ -163,14 +163,15 @@ __device__ __forceinline__ void m_scale(M3<R> &A, cx<R> z) {
 // the eight XCDs in turn, so block b runs on XCD b mod 8; mapping it to
 // logical block (b mod 8) * per + b / 8 gives each XCD (and its L2) one
 // contiguous range of tiles.  The grid is padded to 8 * per blocks.
-__device__ __forceinline__ int remap_block(int b, int nb, int xcd) {
+__host__ __device__ __forceinline__ int remap_block(int b, int nb, int xcd) {
     if (!xcd) return b;
     int per = (nb + 7) >> 3;
     return (b & 7) * per + (b >> 3);
 }
 
-// wave-uniform: which config (exec order) holds tile t
-__device__ __forceinline__ int find_cfg(const int *__restrict__ tile_start, int n, int t) {
+// wave-uniform: which config (exec order) holds tile t (also the block
+// table of the LDS-staged variants)
+__host__ __device__ __forceinline__ int find_cfg(const int *__restrict__ tile_start, int n, int t) {
     int lo = 0, hi = n;   // tile_start[lo] <= t < tile_start[hi]
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;

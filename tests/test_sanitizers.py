@@ -82,3 +82,24 @@ def test_runtime_host_code_under_sanitizers(tmp_path):
     exe = str(tmp_path / "runtime_san")
     run([hipcc, "--offload-arch=gfx950", *host_san, *objs, "-o", exe])
     assert "0 failed checks" in check_clean(exe)
+
+
+def test_stage_index_audit(tmp_path):
+    """Every access of the stage launches replayed on the host with the
+    kernels' own index functions (tests/sanitize/index_audit.cpp): the
+    LDS-staged kernel on per-configuration blocks (whole planes and 256 sites)
+    and the tile-based site kernels, both block orders, all three storages,
+    on the 4x4x12x12 box, the benchmark's extents, ragged and degenerate
+    batches; no access may leave its buffer, LDS block or wave."""
+    hipcc = "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "index_audit")
+    host_san = []
+    for f in SAN_FLAGS:
+        host_san += ["-Xarch_host", f]
+    run([hipcc, "--offload-host-only", "-x", "hip", "-std=c++17", "-O1", "-g", *host_san,
+         "-I", INC, "-I", CSRC, "-Wno-unused-command-line-argument",
+         os.path.join(SAN, "index_audit.cpp"), "-o", exe])
+    out = check_clean(exe)
+    assert " 0 violations" in out, out
