@@ -118,12 +118,18 @@ typedef struct {
 typedef struct tgf_ctx tgf_ctx;
 
 /* Bytes of device workspace needed for n_cfg configurations with geometries
- * geoms[n_cfg] in storage st.  Returns 0 on invalid arguments. */
+ * geoms[n_cfg] (the L x L x 3L x 3L boxes of sec. 3.1, or any extents) in
+ * storage st: per site 1408 (FP64), 704 (FP32 full) or 512 (FP32 12-real)
+ * bytes plus small shared tables.  Returns 0 on invalid arguments. */
 size_t tgf_workspace_bytes(int32_t n_cfg, const tgf_geom *geoms, tgf_storage st);
 
-/* Create a context over caller-owned device memory workspace_dev (at least
- * tgf_workspace_bytes, 256-byte aligned) and the HIP stream hip_stream
- * (hipStream_t; NULL = the null stream).  Configurations start unloaded. */
+/* Create a context for a batch of configurations (the paper's ensembles,
+ * sec. 3.1 and Table A.1) with their extents and twist tensors (the twist
+ * factors Z_{mu nu} of the action, sec. 3.1), over caller-owned device memory
+ * workspace_dev (at least tgf_workspace_bytes, 256-byte aligned) and the HIP
+ * stream hip_stream (hipStream_t; NULL = the null stream).  Configurations
+ * start unloaded.  TGF_E_INVAL for bad geometry, twist, storage or pointers,
+ * TGF_E_SIZE for a workspace that is too small; nothing is touched. */
 tgf_status tgf_create(tgf_ctx **out, int32_t n_cfg, const tgf_geom *geoms, tgf_storage st,
                       void *workspace_dev, size_t workspace_bytes, void *hip_stream);
 
@@ -156,8 +162,9 @@ tgf_status tgf_create_sun(tgf_ctx **out, int32_t nc, int32_t n_cfg, const tgf_ge
                           tgf_storage st, void *workspace_dev, size_t workspace_bytes,
                           void *hip_stream);
 
-/* Copy links of configuration cfg from canonical device memory into the
- * context's storage and set its flow time to t0.  The input is checked:
+/* Copy the SU(3) links U_mu(n) (sec. 3.1) of configuration cfg from
+ * canonical device memory into the context's storage and set its flow time to
+ * t0 (and its step count, which schedules reunitarisation, to 0).  The input is checked:
  * max |U U^+ - 1| and |det U - 1| above 1e-10 (or any non-finite entry)
  * return TGF_E_NOT_SU3 and leave cfg unloaded.  Synchronises. */
 tgf_status tgf_load_links(tgf_ctx *c, int32_t cfg, const void *links_dev, double t0);
@@ -166,8 +173,10 @@ tgf_status tgf_load_links(tgf_ctx *c, int32_t cfg, const void *links_dev, double
  * device pointers), t0[n_cfg] (host).  One check, one synchronisation. */
 tgf_status tgf_load_links_all(tgf_ctx *c, const void *const *links_dev, const double *t0);
 
-/* Write the current links of cfg in canonical layout (FP64; C12 rebuilds row
- * 2).  Enqueued only; the caller synchronises the stream. */
+/* Write the current (flowed) links of cfg, the field V_t of sec. 1, in
+ * canonical layout (FP64; C12 rebuilds row 2): a checkpoint that
+ * tgf_load_links resumes with t0.  Enqueued only; the caller synchronises
+ * the stream. */
 tgf_status tgf_store_links(tgf_ctx *c, int32_t cfg, void *links_dev);
 
 /* Current flow time of cfg. */
@@ -191,11 +200,18 @@ tgf_status tgf_densities(tgf_ctx *c, int32_t cfg, double *e_dev, double *q_dev);
  * the next tgf_flow or tgf_load_links*.  TGF_E_STATE if cfg is not loaded. */
 tgf_status tgf_link_buffer(tgf_ctx *c, int32_t cfg, size_t *offset, size_t *bytes);
 
-/* Measure every loaded configuration at its current flow time:
- * out_host[n_cfg].  Synchronises. */
+/* Measure every loaded configuration at its current flow time: the clover
+ * energy density E (eq. gmunu), t^2 E, the plaquette and action (sec. 3.1)
+ * and the topological charge Q (eq. qlatt), FP64 sums: out_host[n_cfg].
+ * TGF_E_STATE if a configuration is not loaded, TGF_E_NONFINITE if a sum is
+ * not finite.  Synchronises. */
 tgf_status tgf_measure(tgf_ctx *c, tgf_obs *out_host);
 
-/* Flow every configuration from its current t to p->t_end[cfg].  Rows go to
+/* Flow every configuration from its current t to p->t_end[cfg] with the
+ * gradient flow of the twisted Wilson action (sec. 1 and sec. 3.1, the
+ * "Wilson flow discretization"; Luscher's RK3, step p->eps) -- the paper runs
+ * it to sqrt(8t) = c Lt; the benchmark configurations to t = c^2 L^2 / 8 --
+ * measuring as tgf_measure does.  Rows go to
  * rows_host[max_rows][n_cfg] (row-major, config fastest): a row at the start
  * time if it lies on the meas_dt grid, after every step that ends on the
  * grid, and at t_end; a configuration with fewer rows repeats its last row.
@@ -208,7 +224,8 @@ tgf_status tgf_flow(tgf_ctx *c, const tgf_flow_params *p, tgf_obs *rows_host, in
 tgf_status tgf_get_timing(tgf_ctx *c, tgf_timing *out);
 
 /* max |U U^+ - 1| and max |det U - 1| over the current links of cfg (FP64
- * reduction): out[2].  Synchronises. */
+ * reduction): out[2], how far the flowed links are from SU(3) (sec. 3.1).
+ * TGF_E_STATE if cfg is not loaded.  Synchronises. */
 tgf_status tgf_unitarity(tgf_ctx *c, int32_t cfg, double *out);
 
 /* Tune the stage kernel on the loaded links (stage 0 timed with HIP events,
@@ -245,7 +262,8 @@ int32_t tgf_variant_count(void);
 const char *tgf_variant_name(int32_t variant);
 
 /* Plain device copy of bytes (16-byte aligned pointers) on hip_stream: the
- * calibration kernel for HBM counters.  Enqueued only. */
+ * calibration kernel for HBM counters (no counterpart in the paper).
+ * TGF_E_INVAL for misaligned pointers or size.  Enqueued only. */
 tgf_status tgf_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, void *hip_stream);
 
 /* Topological charge per slice of direction dir (0..3; the paper uses a long
