@@ -238,33 +238,6 @@ __device__ __forceinline__ void site_alg_work(const LK &W, gptr<v2<R>> Wout, gpt
     site_alg_update<R, NE, 3>(W, Wout, X, c, g, f[3], beps, ac, a);
 }
 
-// The lower terms of link MU not yet taken from the wave, then the update.
-template <class R, int NE, int MU, class LK>
-__device__ __forceinline__ void wave_update(const LK &W, gptr<v2<R>> Wout, gptr<v2<R>> X,
-                                            const CfgDesc &c, const Geo &g, const R f[8],
-                                            R beps, R ac, const StageArgs &a, unsigned done) {
-    R k[8];
-#pragma unroll
-    for (int t = 0; t < 8; t++) k[t] = f[t];
-#pragma unroll
-    for (int nu = 0; nu < 4; nu++) {
-        if (nu == MU || ((done >> (4 * MU + nu)) & 1u)) continue;
-        const int imn = g.i + g.dn(nu);
-        R2<R> P = r2_of(W.own(MU, g.i));
-        P = r2_mul_nd(P, W(nu, imn + g.up(MU)));
-        P = r2_mul_nd(P, W(MU, imn));
-        P = r2_mul_nn(P, W(nu, imn));
-        const int kt = twist_exp(c, MU, nu);
-        if (kt && g.n(MU) == 0 && g.back(nu) == 0) r2_scale(P, omega_pow<R>(kt));
-        R r[8];
-        r2_raw(P, r);
-#pragma unroll
-        for (int t = 0; t < 8; t++) k[t] += r[t];
-    }
-    update_link_z<R, NE>(W, Wout, X, c.stride, MU, g.i, raw_to_alg(k, -beps), ac, a.stage,
-                         reunit_now(a, c));
-}
-
 // site_alg_work with in-wave plaquette reuse (FP32): a lane's lower staple
 // term of link mu in plane nu is the conjugated plaquette of site n - nu;
 // when that site lies in the same wave for every active lane (the (n0, n1)
@@ -326,10 +299,41 @@ __device__ __forceinline__ void site_wave_work(const LK &W, gptr<v2<R>> Wout, gp
                 done |= 1u << (4 * nu + mu);
             }
         }
-    wave_update<R, NE, 0>(W, Wout, X, c, g, f[0], beps, ac, a, done);
-    wave_update<R, NE, 1>(W, Wout, X, c, g, f[1], beps, ac, a, done);
-    wave_update<R, NE, 2>(W, Wout, X, c, g, f[2], beps, ac, a, done);
-    wave_update<R, NE, 3>(W, Wout, X, c, g, f[3], beps, ac, a, done);
+    // the remaining lower terms grouped by direction nu: U_nu(n - nu), which
+    // closes all three loops of that direction, is fetched and its third row
+    // rebuilt once; the scheduling fences keep the compiler from hoisting the
+    // next direction's neighbour loads (and their registers) over a group
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        unsigned todo = 0;
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++)
+            if (mu != nu && !((done >> (4 * mu + nu)) & 1u)) todo |= 1u << mu;
+        if (!todo) continue;
+        __builtin_amdgcn_sched_barrier(0);
+        const int imn = i + g.dn(nu);
+        const M3<R> V = W(nu, imn);
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+            if (mu == nu || !((todo >> mu) & 1u)) continue;
+            R2<R> P = r2_of(W.own(mu, i));
+            P = r2_mul_nd(P, W(nu, imn + g.up(mu)));
+            P = r2_mul_nd(P, W(mu, imn));
+            P = r2_mul_nn(P, V);
+            const int kt = twist_exp(c, mu, nu);
+            if (kt && g.n(mu) == 0 && g.back(nu) == 0) r2_scale(P, omega_pow<R>(kt));
+            R r[8];
+            r2_raw(P, r);
+#pragma unroll
+            for (int t = 0; t < 8; t++) f[mu][t] += r[t];
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const int rn = reunit_now(a, c);
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++)
+        update_link_z<R, NE>(W, Wout, X, c.stride, mu, i, raw_to_alg(f[mu], -beps), ac, a.stage,
+                             rn);
 }
 
 template <class R, int NE>
@@ -481,7 +485,7 @@ __device__ __forceinline__ void site_lds_body(const StageArgs &a) {
     }
 }
 
-// Waves per SIMD: FP32 12-real three (168 registers, a few spilled; three
+// Waves per SIMD: FP32 12-real three (147 registers, none spilled; three
 // 48 KB blocks per CU), FP32 full two (72 KB blocks), FP64 one (144 KB).
 // With the in-block neighbours in LDS the third 12-real wave pays: 6.5%
 // shorter stage launches than the two-wave build, where without LDS a third

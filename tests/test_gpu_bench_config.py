@@ -36,12 +36,14 @@ def batch():
     v = f.autotune(None)
     f.load_all(inputs)
     rows = f.flow(bench.EPS, t_end, 0.1, 10)
-    print(f"  batch flowed with variant {tgf.variant_names()[v]}", flush=True)
-    return cfgs, inputs, rows, v
+    blocks = [f.block(k) for k in range(len(cfgs))]
+    print(f"  batch flowed with variant {tgf.variant_names()[v]}, work-group shapes "
+          f"{sorted(set(zip([c[0][0] for c in cfgs], blocks)))}", flush=True)
+    return cfgs, inputs, rows, v, blocks
 
 
 def test_batch_vs_fp64_gpu(batch):
-    cfgs, inputs, rows, _ = batch
+    cfgs, inputs, rows, _, _ = batch
     g = tgf.Flow([c[0] for c in cfgs], "f64")
     g.load_all(inputs)
     r64 = g.flow(bench.EPS, [c[3] for c in cfgs], 0.1, 0)
@@ -54,7 +56,7 @@ def test_batch_vs_fp64_gpu(batch):
 
 @pytest.mark.parametrize("k", [0, 64, 80])
 def test_batch_samples_vs_oracle(batch, k):
-    cfgs, inputs, rows, _ = batch
+    cfgs, inputs, rows, _, _ = batch
     dims, _, _, t_end = cfgs[k]
     t_stop = t_end if dims[0] <= 8 else 0.2
     ref = oracle.flow(inputs[k].cpu().numpy().copy(), dims, bench.EPS, t_stop, 0.1)
@@ -71,10 +73,14 @@ def test_batch_samples_vs_oracle(batch, k):
 
 @pytest.mark.parametrize("k", [5, 70, 90])
 def test_batch_samples_equal_solo(batch, k):
-    cfgs, inputs, rows, v = batch
+    # a configuration's arithmetic is fixed by the stage variant and its
+    # work-group shape (which in-wave reuse paths its waves take), so the solo
+    # run takes both from the tuned batch
+    cfgs, inputs, rows, v, blocks = batch
     dims, _, _, t_end = cfgs[k]
     f = tgf.Flow([dims], "f32c12")
     f.set_variant(v)
+    f.set_block(0, blocks[k])
     f.load(0, inputs[k])
     solo = f.flow(bench.EPS, t_end, 0.1, 10)
     assert np.array_equal(rows[: solo.shape[0], k], solo[:, 0])

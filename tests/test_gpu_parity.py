@@ -382,4 +382,5 @@ def test_autotune_picks_a_variant(tmp_path):
     h = tgf.Flow([D2], "f32c12")
     h.load(0, U)
     h.set_variant(v)
+    h.set_block(0, f.block(0))
     assert np.array_equal(r1, h.flow(0.01, 0.05, 0.0))
