@@ -11,7 +11,8 @@ Default workload (ensemble batch): 64 configurations of 8x8x24x24, 16 of
 exp(i eps H) with eps in {0.2, 0.3, 0.4}, flowed to c = 0.3 (t_end =
 c^2 L^2 / 8), FP32 storage with 12-real links, FP64 reunitarisation every
 10 steps.  The same batch is also flowed with the plain FP64 path.
-`--workload large` runs one 32x32x96x96 box (t_end 11.52, measured every 0.1).
+`--workload large` runs one 32x32x96x96 box (t_end 11.52, measured every 0.1;
+with --large-steps N only its first N steps).
 
 Prints one JSON line (metric, value = site-updates/s, roofline, cpu_baseline).
 """
@@ -454,7 +455,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mc", action="store_true")
     ap.add_argument("--no-large", action="store_true")
-    ap.add_argument("--large-steps", type=int, default=LARGE_STEPS)
+    ap.add_argument("--large-steps", type=int, default=None,
+                    help=f"steps of the 32x32x96x96 leg (default {LARGE_STEPS}); with "
+                         "--workload large, flow only this many steps (default: the whole flow)")
     ap.add_argument("--mc-reps", type=int, default=3)
     ap.add_argument("--mode", choices=("flow", "copy", "mc", "sun"), default="flow",
                     help="copy: time the library's plain HBM copy kernel (counter calibration); "
@@ -484,7 +487,7 @@ def main():
         sun_mode(tgf, torch, args)
         return
 
-    cfgs = batch_workload() if args.workload == "batch" else large_workload()
+    cfgs = batch_workload() if args.workload == "batch" else large_workload(args.large_steps)
     args.no_large = args.no_large or args.workload != "batch"
     log(f"generating {len(cfgs)} configurations on the GPU")
     inputs = make_inputs(cfgs, "cuda")
@@ -523,7 +526,9 @@ def main():
             "workload": ("ensemble batch: 64 x 8x8x24x24 + 16 x 6x6x18x18 + 16 x 10x10x30x30, "
                          "twist n01=1, near-identity links eps {0.2,0.3,0.4}, flow to c=0.3")
                         if args.workload == "batch" else
-                        "large box 32x32x96x96, twist n01=1, Haar links, flow to c=0.3",
+                        ("large box 32x32x96x96, twist n01=1, Haar links, " +
+                         ("flow to c=0.3" if args.large_steps is None else
+                          f"first {args.large_steps} RK3 steps of the flow to c=0.3")),
             "n_configs": len(cfgs),
             "sites": sites,
             "site_updates_per_step": site_updates,
@@ -558,8 +563,9 @@ def main():
         torch.cuda.empty_cache()
 
     if args.workload == "batch" and not args.no_large:
-        log(f"large box: first {args.large_steps} steps of 32x32x96x96, FP32 12-real and FP64")
-        out["large"] = large_leg(tgf, torch, np, args.large_steps)
+        large_steps = args.large_steps or LARGE_STEPS
+        log(f"large box: first {large_steps} steps of 32x32x96x96, FP32 12-real and FP64")
+        out["large"] = large_leg(tgf, torch, np, large_steps)
 
     if not args.no_mc:
         log("timing the Monte Carlo on the same geometry")

@@ -442,7 +442,7 @@ __device__ __forceinline__ void site_lds_body(const StageArgs &a) {
     if (b >= a.n_blocks) return;                           // whole work-group
     const int ci = find_cfg(a.blk_start, a.n_act, b);      // work-group uniform
     const CfgDesc c = a.cfgs[ci];
-    const int base = (b - a.blk_start[ci]) * c.blk;
+    const int base = block_order(b - a.blk_start[ci], c) * c.blk;
     const int nblk = min(c.blk, c.V - base);               // sites base .. base + nblk - 1
     const int i = base + (int)threadIdx.x;
 

@@ -180,6 +180,24 @@ __host__ __device__ __forceinline__ int find_cfg(const int *__restrict__ tile_st
     return lo;
 }
 
+// Launch order of a configuration's LDS-staged work-groups: its j-th
+// work-group takes block block_order(j, c), the sites blk * block_order(j, c)
+// onwards.  In site order (c.chunk = 0) a block's neighbours in direction 3
+// are d0 d1 d2 / blk blocks away; on large boxes that is more work-groups
+// than an XCD holds at a time, so the neighbour links have left its L2 when
+// they are read.  There the n3 slices are cut into columns of c.chunk blocks
+// (along n2) and each column is walked through all n3 before the next: the
+// direction-3 neighbours are c.chunk blocks away.  A one-to-one map of
+// 0 .. V/blk - 1; needs d0 d1 d2 to be a multiple of blk * c.chunk.
+__host__ __device__ __forceinline__ int block_order(int j, const CfgDesc &c) {
+    if (!c.chunk) return j;
+    const int slice = c.d[0] * c.d[1] * c.d[2] / c.blk;   // blocks per n3 slice
+    const int col = c.chunk * c.d[3];                     // blocks per column
+    const int k = j / col, r = j - k * col;
+    const int n3 = r / c.chunk;
+    return n3 * slice + k * c.chunk + (r - n3 * c.chunk);
+}
+
 // A wave-uniform pointer taken through readfirstlane: the result is known to
 // be uniform (an SGPR pair) and opaque to re-association, so that
 // `sgpr_base(uniform) + lane offset` stays a global access with an SGPR base

@@ -41,6 +41,7 @@ struct CfgDesc {
     int32_t n_steps;      // n_full + (short final step ? 1 : 0)
     int32_t reunit_phase; // steps since the load, before this flow, mod reunit_every
     int32_t blk;          // sites per work-group of the LDS-staged stage variants (<= 256)
+    int32_t chunk;        // their launch order: 0 = site order, else columns of chunk blocks
     double eps_last;      // size of the short final step (0 if none)
     double t0;            // flow time at the start of this flow
     void *W[2];

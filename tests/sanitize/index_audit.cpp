@@ -1,7 +1,7 @@
 // Host audit of the stage kernels' index arithmetic (test infrastructure).
 //
 // Replays, on the CPU and with the kernels' own index functions (make_geo,
-// Geo::up/dn, remap_block, find_cfg from lattice_dev.h), every work-group,
+// Geo::up/dn, remap_block, find_cfg, block_order from lattice_dev.h), every work-group,
 // wave and lane of the stage launches -- the LDS-staged kernel on its
 // per-configuration block table and the tile-based site kernels on the tile
 // table, each in both block orders -- and checks every link, accumulator and
@@ -9,7 +9,8 @@
 // offsets inside the configuration's buffers (the FP32 paired-entry layout
 // and the FP64 entry planes), LDS slots inside the staged block, the source
 // lanes of the in-wave plaquette reuse among the wave's active lanes, the
-// XCD block remap as a one-to-one map, and every site updated exactly once.
+// XCD block remap and the column launch order of large boxes as one-to-one
+// maps, and every site updated exactly once.
 // The access list per lane follows site_wave_work / site_alg_work /
 // update_link_z in kernels.hip.  Built host-only with AddressSanitizer and
 // UndefinedBehaviorSanitizer by tests/test_sanitizers.py.
@@ -43,6 +44,16 @@ static int default_blk(const int d[4]) {   // the runtime's default shape rule
     return k * plane >= kBlock / 2 ? k * plane : kBlock;
 }
 
+static int chunk_rule(const int d[4], int blk) {   // the runtime's column rule (block_chunk)
+    const long long s = (long long)d[0] * d[1] * d[2];
+    if (s % blk) return 0;
+    const long long slice = s / blk;
+    if (slice <= 64) return 0;
+    for (int ch = 16; ch >= 4; ch--)
+        if (slice % ch == 0) return ch;
+    return 0;
+}
+
 static Case make_case(const std::vector<std::array<int, 4>> &dims, int ne, int rbytes, bool planes) {
     Case k;
     k.ne = ne;
@@ -53,6 +64,7 @@ static Case make_case(const std::vector<std::array<int, 4>> &dims, int ne, int r
         c.V = d[0] * d[1] * d[2] * d[3];
         c.stride = (c.V + 255) / 256 * 256;
         c.blk = planes ? default_blk(c.d) : kBlock;
+        c.chunk = chunk_rule(c.d, c.blk);
         k.c.push_back(c);
     }
     return k;
@@ -131,7 +143,7 @@ static void lds_launch(const Case &k, bool xcd, bool wave_reuse) {
     for (int a = 0; a < n; a++) bs[a + 1] = bs[a] + (k.c[a].V + k.c[a].blk - 1) / k.c[a].blk;
     const int nb = bs[n];
     const int grid = xcd ? (nb + 7) / 8 * 8 : nb;
-    std::vector<int> seen(nb, 0);
+    std::vector<int> seen(nb, 0), order_seen(nb, 0);
     std::vector<std::vector<int>> cover(n);
     for (int a = 0; a < n; a++) cover[a].assign(k.c[a].V, 0);
     std::vector<Access> acc, reuse;
@@ -143,7 +155,10 @@ static void lds_launch(const Case &k, bool xcd, bool wave_reuse) {
         const int ci = find_cfg(bs.data(), n, b);
         if (!(bs[ci] <= b && b < bs[ci + 1])) { fail("block config", ci, b, b); continue; }
         const CfgDesc &c = k.c[ci];
-        const int base = (b - bs[ci]) * c.blk;
+        const int ob = block_order(b - bs[ci], c);
+        if (ob < 0 || ob >= bs[ci + 1] - bs[ci]) { fail("block order", ci, b, ob); continue; }
+        order_seen[bs[ci] + ob]++;
+        const int base = ob * c.blk;
         const int nblk = std::min(c.blk, c.V - base);
         if (nblk < 1 || c.blk > kBlock) { fail("block size", ci, base, nblk); continue; }
         for (int t = 0; t < nblk; t++) {       // staging: LDS slot t <- site base + t
@@ -201,8 +216,10 @@ static void lds_launch(const Case &k, bool xcd, bool wave_reuse) {
             }
         }
     }
-    for (int b = 0; b < nb; b++)
+    for (int b = 0; b < nb; b++) {
         if (seen[b] != 1) fail("block coverage", -1, b, seen[b]);
+        if (order_seen[b] != 1) fail("block order coverage", -1, b, order_seen[b]);
+    }
     for (int a = 0; a < n; a++)
         for (int i = 0; i < k.c[a].V; i++)
             if (cover[a][i] != 1) fail("site coverage", a, i, cover[a][i]);
@@ -244,12 +261,45 @@ static void tile_launch(const Case &k, bool xcd) {
             if (cover[a][i] != 1) fail("site coverage (tiles)", a, i, cover[a][i]);
 }
 
+// block_order alone: a one-to-one map of each configuration's blocks, over a
+// range of extents and work-group shapes where the column order applies.
+static void order_check() {
+    int used = 0;
+    for (int d0 : {4, 8, 12, 16, 24, 32, 48})
+        for (int d2 : {8, 24, 40, 96, 144})
+            for (int d3 : {2, 5, 96}) {
+                const int d[4] = {d0, d0, d2, d3};
+                for (int blk : {kBlock, default_blk(d)}) {
+                    CfgDesc c{};
+                    for (int m = 0; m < 4; m++) c.d[m] = d[m];
+                    c.V = d0 * d0 * d2 * d3;
+                    c.blk = blk;
+                    c.chunk = chunk_rule(c.d, blk);
+                    if (!c.chunk) continue;
+                    used++;
+                    const int nb = (c.V + blk - 1) / blk;
+                    std::vector<int> hit(nb, 0);
+                    for (int j = 0; j < nb; j++) {
+                        const int b = block_order(j, c);
+                        checked++;
+                        if (b < 0 || b >= nb) { fail("order range", 0, j, b); continue; }
+                        hit[b]++;
+                    }
+                    for (int b = 0; b < nb; b++)
+                        if (hit[b] != 1) fail("order coverage", 0, b, hit[b]);
+                }
+            }
+    if (used < 20) fail("too few column-order shapes", 0, used, used);
+}
+
 int main() {
+    order_check();
     const std::vector<std::vector<std::array<int, 4>>> batches = {
         {{4, 4, 12, 12}},                                                 // the faulting case's box
         {{6, 6, 18, 18}, {8, 8, 24, 24}, {10, 10, 30, 30}},                // the benchmark's extents
         {{4, 4, 12, 12}, {3, 5, 4, 7}, {10, 10, 6, 6}, {6, 6, 18, 18}},   // ragged, straddling
         {{2, 2, 2, 2}, {8, 8, 4, 6}, {12, 12, 6, 4}, {32, 32, 8, 4}},     // degenerate, planes > 256
+        {{16, 16, 72, 2}, {6, 6, 18, 18}, {16, 16, 96, 3}},               // column launch order
     };
     for (auto &dims : batches)
         for (int st = 0; st < 3; st++)

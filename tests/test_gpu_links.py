@@ -101,6 +101,29 @@ def test_links_every_plane_twisted(storage):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f32c12"])
+def test_links_column_launch_order(storage):
+    """A box whose n3 slice spans more than 64 LDS work-groups (16x16x72:
+    72 blocks of 256 sites) runs them in columns of 12 blocks along n2, each
+    column through all n3 (block_order): links entry by entry against the
+    oracle after two steps, and the same box in a batch with a site-order
+    box (8x8x24x24) gives bitwise its solo links."""
+    dims, other = (16, 16, 72, 4), (8, 8, 24, 24)
+    U = gen.near_identity(dims, 0.3, seed=91).numpy().copy()
+    W = gen.near_identity(other, 0.3, seed=92).numpy().copy()
+    ref = U.copy()
+    oracle.flow(ref, dims, 0.01, 0.02, 0.0)
+    got, _ = gpu_links(dims, storage, U, 0.01, 0.02, "site_lds_xcd")
+    d = np.abs(got - ref).max()
+    say(f"  column order {storage}: max |dU| {d:.3g}")
+    assert d <= (1e-13 if storage == "f64" else 3e-6)      # two steps
+    f = tgf.Flow([other, dims], storage)
+    f.set_variant(variant_index("site_lds_xcd"))
+    f.load_all([torch.from_numpy(W).cuda(), torch.from_numpy(U).cuda()])
+    f.flow(0.01, 0.02, 0.0, 0)
+    assert np.array_equal(f.store(1).cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32c12"])
 @pytest.mark.parametrize("case", ["d1", "twisted"])
 def test_densities(storage, case):
     if case == "d1":
