@@ -545,6 +545,21 @@ def main():
         "hbm_frac_whole_pass": round(whole_gbs / HBM_PEAK_GBS, 4),
     }
 
+    if not args.no_fp64 and args.storage == "f32c12":
+        log("timing the FP32 full-matrix storage on the same workload")
+        del f
+        torch.cuda.empty_cache()
+        k32 = max(1, args.steps // 3)
+        f32, rows32, dt32 = time_flows(tgf, torch, cfgs, inputs, "f32", k32, 1)
+        v32 = tgf.variant_names()[f32.variant]
+        out["fp32_full"] = {"value": round(site_updates / dt32, 1), "unit": "site-updates/s",
+                            "ms_per_step": round(dt32 * 1e3, 3), "steps": k32, "variant": v32,
+                            "bytes_per_site_step": bytes_per_site_step("f32", v32),
+                            "lds_block_sites": block_shapes(f32, cfgs)}
+        f = f32            # freed with the FP64 leg below
+    else:
+        rows32, dt32 = None, None
+
     if not args.no_fp64 and args.storage != "f64":
         log("timing FP64 plain path on the same workload")
         del f
@@ -559,6 +574,10 @@ def main():
                              "lds_block_sites": block_shapes(f64, cfgs)}
         out["speedup_vs_fp64_plain"] = round(dt64 / dt, 3)
         out["t2E_max_rel_err_vs_fp64_gpu"] = float(rel.max())
+        if rows32 is not None:
+            rel32 = np.abs(rows32[:, :, 2] - rows64[:, :, 2])[pos] / np.abs(rows64[:, :, 2][pos])
+            out["fp32_full"]["speedup_vs_fp64_plain"] = round(dt64 / dt32, 3)
+            out["fp32_full"]["t2E_max_rel_err_vs_fp64_gpu"] = float(rel32.max())
         del f64
         torch.cuda.empty_cache()
 

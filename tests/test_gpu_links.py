@@ -123,6 +123,29 @@ def test_links_column_launch_order(storage):
     assert np.array_equal(f.store(1).cpu().numpy(), got)
 
 
+def test_large_box_one_step_vs_oracle():
+    """The 32x32x96x96 Haar box of the benchmark's large leg (9.4M sites,
+    column launch order, site_lds_xcd): one RK3 step, every link entry of
+    the FP64 and the FP32 12-real flows against the oracle's step."""
+    dims = (32, 32, 96, 96)
+    U = gen.haar(dims, seed=5, device="cuda")
+    ref = U.cpu().numpy().copy()
+    say("  D5: oracle step (16 threads)")
+    oracle.rk3_step(ref, dims, 0.01)
+    ref_dev = torch.from_numpy(ref).cuda()
+    del ref
+    for storage in ("f64", "f32c12"):
+        f = tgf.Flow([dims], storage)
+        f.set_variant(variant_index("site_lds_xcd"))
+        f.load(0, U)
+        f.flow(0.01, 0.01, 0.0, 10)
+        d = (f.store(0) - ref_dev).abs().max().item()
+        say(f"  D5 one step {storage}: max |dU| {d:.3g}")
+        assert d <= LINK_BAR_1[storage]
+        del f
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f32c12"])
 @pytest.mark.parametrize("case", ["d1", "twisted"])
 def test_densities(storage, case):
