@@ -125,12 +125,20 @@ def flops_per_site_step(storage, variant):
     return 3 * flops_per_site_stage(storage, variant)
 
 
-def kernel_source_hash():
+def kernel_source_hash(root=ROOT):
+    """Hash of the stage kernels' code (comments and blank lines left out, so
+    that a profile stays valid across comment edits but not across a change
+    of the code)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hip", "lattice_dev.h", "su3_dev.h", "layout.h"):
-        with open(os.path.join(ROOT, "paper_2107_03747_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(root, "paper_2107_03747_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        lines = [ln.rstrip() for ln in text.splitlines() if ln.strip()]
+        h.update("\n".join(lines).encode())
     return h.hexdigest()[:16]
 
 

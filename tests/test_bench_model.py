@@ -49,3 +49,20 @@ def test_mc_and_sun_models():
     assert bench.MC_FLOPS_PER_LINK == 3402
     for n in (2, 3, 4, 8):
         assert bench.sun_bytes_per_site_step(n) == 640 * n * n
+
+
+def test_kernel_source_hash_ignores_comments_only(tmp_path):
+    """The hash that ties a profile to the kernel code: unchanged by comment
+    and blank-line edits, changed by any edit of the code."""
+    import shutil
+    src = os.path.join(ROOT, "paper_2107_03747_amd", "csrc")
+    dst = tmp_path / "paper_2107_03747_amd" / "csrc"
+    shutil.copytree(src, dst)
+    h0 = bench.kernel_source_hash(str(tmp_path))
+    assert h0 == bench.kernel_source_hash()
+    k = dst / "kernels.hip"
+    text = k.read_text()
+    k.write_text("// a new comment line\n\n" + text.replace("namespace tgf {", "namespace tgf {  /* x */", 1))
+    assert bench.kernel_source_hash(str(tmp_path)) == h0
+    k.write_text(text.replace("kRkA[3] = {0.0,", "kRkA[3] = {0.0 ,", 1))
+    assert bench.kernel_source_hash(str(tmp_path)) != h0
