@@ -367,7 +367,9 @@ def sun_mode(tgf, torch, args):
     v = f.autotune(None) if args.variant is None else args.variant
     f.set_variant(v)
     rows_per_lane = int(tgf.tgf_sun_rows_per_lane(N, v))
-    log(f"SU({N}): variant {v} ({rows_per_lane} rows per lane)")
+    lds = int(tgf.tgf_sun_variant_lds(N, v)) == 1
+    log(f"SU({N}): variant {v} ({rows_per_lane} rows per lane, "
+        f"{'LDS operands' if lds else 'permutes'})")
     f.flow(EPS, t_end, 0.0)                      # warm-up (graph capture)
     times = []
     for _ in range(max(1, args.steps // 5)):
@@ -397,7 +399,9 @@ def sun_mode(tgf, torch, args):
                    "n_configs": n_cfg, "sites": n_cfg * V},
         "t2E_last_cfg0": float(rows[-1, 0, 2]),
         "rows_per_lane": rows_per_lane,
-        "roofline": {"kernel": f"sun_stage_kernel<{N}, {rows_per_lane}>", "bound": "alu",
+        "operands": "lds" if lds else "permutes",
+        "roofline": {"kernel": (f"sun_stage_lds_kernel<{N}>" if lds
+                                else f"sun_stage_kernel<{N}, {rows_per_lane}>"), "bound": "alu",
                      "achieved": round(tflops, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
                      "unit": "TFLOP/s", "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
                      "hbm_gbs_algorithmic": round(gbs, 1),

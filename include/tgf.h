@@ -147,17 +147,22 @@ tgf_status tgf_create(tgf_ctx **out, int32_t n_cfg, const tgf_geom *geoms, tgf_s
  *   - plaq = (1/(6 nc V)) sum_n sum_{mu<nu} Re Tr[Z^* P], action =
  *     sum_n sum_{mu<nu} Re Tr[1 - Z^* P], force -P_ah with the trace/nc part;
  *   - the variants are the rows of each link matrix held per lane (a link
- *     spread over nc / rows lanes, rows = nc: one thread per link):
- *     tgf_set_variant accepts -1 .. tgf_sun_variant_count(nc) - 1 and
+ *     spread over nc / rows lanes, rows = nc: one thread per link), and how a
+ *     product reaches the rows other lanes hold: cross-lane permutes, or (the
+ *     LDS-operand variant, one row per lane) a per-wave LDS copy of the right
+ *     operand; tgf_set_variant accepts -1 .. tgf_sun_variant_count(nc) - 1 and
  *     tgf_autotune times them; tgf_mc and tgf_slice_charge return
  *     TGF_E_UNSUPPORTED.
  * tgf_workspace_bytes_sun returns 0 on invalid arguments. */
 size_t tgf_workspace_bytes_sun(int32_t nc, int32_t n_cfg, const tgf_geom *geoms,
                                tgf_storage st);
-/* Number of SU(nc) stage variants (0 for nc outside 2..8), and the matrix rows
- * per lane of variant v (-1 = the default, 0; returns 0 for no such variant). */
+/* Number of SU(nc) stage variants (0 for nc outside 2..8), the matrix rows
+ * per lane of variant v (-1 = the default, 0; returns 0 for no such variant),
+ * and whether v reads product operands from LDS (1) or through cross-lane
+ * permutes (0; -1 for no such variant). */
 int32_t tgf_sun_variant_count(int32_t nc);
 int32_t tgf_sun_rows_per_lane(int32_t nc, int32_t variant);
+int32_t tgf_sun_variant_lds(int32_t nc, int32_t variant);
 tgf_status tgf_create_sun(tgf_ctx **out, int32_t nc, int32_t n_cfg, const tgf_geom *geoms,
                           tgf_storage st, void *workspace_dev, size_t workspace_bytes,
                           void *hip_stream);

@@ -89,9 +89,12 @@ hipError_t launch_check_final(hipStream_t s, const double *partials, int ntiles,
 
 // General SU(N), FP64 full storage [mu][N^2][stride], 2 <= nc <= 8 (sun.hip).
 // Same tile table, ping-pong and partials conventions as the SU(3) launchers.
-// variant selects the rows held per lane (sun_rows_per_lane); -1 = 0.
+// variant selects the rows held per lane (sun_rows_per_lane) and whether the
+// products exchange rows through cross-lane permutes or LDS (sun_variant_lds);
+// -1 = 0.
 int sun_variant_count(int nc);
 int sun_rows_per_lane(int nc, int variant);   // 0 if the variant does not exist
+int sun_variant_lds(int nc, int variant);     // 1 LDS operands, 0 permutes, -1 no such variant
 hipError_t launch_stage_sun(int nc, int variant, hipStream_t s, const CfgDesc *cfgs,
                             const int *tile_start, int n_act, int n_tiles, int step, int stage,
                             double eps);

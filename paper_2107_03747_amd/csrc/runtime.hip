@@ -987,6 +987,11 @@ int32_t tgf_sun_rows_per_lane(int32_t nc, int32_t variant) {
     return sun_rows_per_lane(nc, variant);
 }
 
+int32_t tgf_sun_variant_lds(int32_t nc, int32_t variant) {
+    if (nc < 2 || nc > 8) return -1;
+    return sun_variant_lds(nc, variant);
+}
+
 const char *tgf_variant_name(int32_t v) {
     if (v < 0 || v >= V_COUNT) return "default";
     return variant_name(v);

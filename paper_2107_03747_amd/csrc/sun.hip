@@ -256,11 +256,70 @@ __device__ __forceinline__ int tw_exp(const CfgDesc &c, int mu, int nu) {
     return t ? N - t : 0;
 }
 
+// exp(2 pi i k / N) for N = 2..8, k = 0..N-1 as (cos, sin), the exact values
+// rounded to double (evaluated to 60 digits; zeros and units exact).  A table
+// read with a wave-uniform index keeps the trigonometric code, and the private
+// memory its argument reduction uses, out of the flow kernels.
+__constant__ double kTwistPhase[9][8][2] = {
+    {  // unused
+        {0.0, 0.0}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+    },
+    {  // unused
+        {0.0, 0.0}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+    },
+    {  // N = 2
+        {1.0, 0.0}, {-1.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+    },
+    {  // N = 3
+        {1.0, 0.0}, {-0.5, 0.8660254037844386},
+        {-0.5, -0.8660254037844386}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+    },
+    {  // N = 4
+        {1.0, 0.0}, {0.0, 1.0},
+        {-1.0, 0.0}, {0.0, -1.0},
+        {0.0, 0.0}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+    },
+    {  // N = 5
+        {1.0, 0.0}, {0.30901699437494745, 0.9510565162951535},
+        {-0.8090169943749475, 0.5877852522924731}, {-0.8090169943749475, -0.5877852522924731},
+        {0.30901699437494745, -0.9510565162951535}, {0.0, 0.0},
+        {0.0, 0.0}, {0.0, 0.0},
+    },
+    {  // N = 6
+        {1.0, 0.0}, {0.5, 0.8660254037844386},
+        {-0.5, 0.8660254037844386}, {-1.0, 0.0},
+        {-0.5, -0.8660254037844386}, {0.5, -0.8660254037844386},
+        {0.0, 0.0}, {0.0, 0.0},
+    },
+    {  // N = 7
+        {1.0, 0.0}, {0.6234898018587335, 0.7818314824680298},
+        {-0.2225209339563144, 0.9749279121818236}, {-0.9009688679024191, 0.4338837391175581},
+        {-0.9009688679024191, -0.4338837391175581}, {-0.2225209339563144, -0.9749279121818236},
+        {0.6234898018587335, -0.7818314824680298}, {0.0, 0.0},
+    },
+    {  // N = 8
+        {1.0, 0.0}, {0.7071067811865476, 0.7071067811865476},
+        {0.0, 1.0}, {-0.7071067811865476, 0.7071067811865476},
+        {-1.0, 0.0}, {-0.7071067811865476, -0.7071067811865476},
+        {0.0, -1.0}, {0.7071067811865476, -0.7071067811865476},
+    },
+};
+
 template <int N>
 __device__ __forceinline__ cx<double> zphase(int t) {
-    double s, co;
-    sincospi(2.0 * (double)t / (double)N, &s, &co);
-    return {co, s};
+    return {kTwistPhase[N][t][0], kTwistPhase[N][t][1]};
 }
 
 // ---------------------------------------------------------------------------
@@ -414,7 +473,7 @@ __global__ __launch_bounds__(256) void sun_stage_kernel(SunStageArgs a) {
     if (tile >= a.n_tiles) return;
     const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ci = find_cfg(a.tile_start, a.n_act, tile);
-    const CfgDesc c = a.cfgs[ci];
+    const CfgDesc &c = a.cfgs[ci];   // in global memory: the twist entries are read with run-time indices
     constexpr int L = N / R, G = 64 / L;
     const int lane = threadIdx.x & 63;
     const int g = lane / L;
@@ -553,7 +612,7 @@ __global__ __launch_bounds__(256) void sun_measure_kernel(const CfgDesc *__restr
     if (tile >= n_tiles) return;
     const int ci = find_cfg(tile_start, n_cfg, tile);
     if (slots[ci].row < 0) return;
-    const CfgDesc c = cfgs[ci];
+    const CfgDesc &c = cfgs[ci];     // in global memory: the twist entries are read with run-time indices
     const int sel = buf_sel < 0 ? c.cur : ((c.cur + buf_sel) & 1);
     gptr<const v2<double>> W = as_global<double>((const void *)(sel ? c.W[1] : c.W[0]));
     constexpr int L = N / R, G = MeasShape<N, R>::G, SPW = MeasShape<N, R>::SPW;
@@ -693,23 +752,474 @@ __global__ __launch_bounds__(64) void sun_check_kernel(const void *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// launchers.  Rows per lane for each N, in variant order (variant 0 is the
-// default): the first entry is the fastest measured on the benchmark boxes.
+// LDS-operand variant.  One row per lane (a link over N consecutive lanes,
+// G = 64 / N links per wave), and the right operand of every product is read
+// from an LDS slot of the wave that the owning lanes have filled with their
+// rows: one 16-byte LDS read per complex multiply-add, against four 4-byte
+// cross-lane permutes in the permute variants, and the products run as short
+// loops over rows of the operand, so no link matrix is held whole in
+// registers.  Each wave owns two slots of G padded link matrices (one complex
+// of padding per link puts the G links of a read in different banks).  LDS
+// operations of a wave execute in order, so a slot written by a wave is read
+// by the same wave without a barrier, and the wave barriers only keep the
+// compiler from moving accesses across a fill.
 
-__host__ __device__ constexpr int sun_rows(int nc, int v) {
-    // N:         2        3        4                 5   6        7   8
-    return nc == 2 ? (v == 0 ? 2 : 1)
-         : nc == 3 ? (v == 0 ? 3 : 1)
-         : nc == 4 ? (v == 0 ? 2 : (v == 1 ? 1 : 4))
-         : nc == 6 ? (v == 0 ? 2 : 1)
-         : 1;
+template <int N>
+struct LdsShape {
+    static constexpr int G = 64 / N;         // links per wave
+    static constexpr int LS = N * N + 1;     // complex per link in a slot
+    static constexpr int SLOT = G * LS;      // complex per slot
+};
+
+template <int N>
+struct Row {
+    cx<double> e[N];
+};
+
+template <int N>
+__device__ __forceinline__ Row<N> row_zero() {
+    Row<N> o;
+#pragma unroll
+    for (int j = 0; j < N; j++) o.e[j] = {0.0, 0.0};
+    return o;
+}
+
+// this lane's row r of its link g: s[0], s[1] the link's matrices in the two slots
+template <int N>
+struct LaneRow {
+    v2<double> *s[2];
+    int r;
+    int base;   // first lane of the link
+};
+
+// Compiler fences.  The products end each row of their operand with one that
+// takes the accumulators through an empty asm statement: the arithmetic of
+// that row is then done before it, and no load or store moves across it
+// (neither in the IR passes nor in the scheduler).  Without them the compiler
+// reads a whole operand matrix before the first multiply-add, which holds it
+// in registers and spills.
+__device__ __forceinline__ void lds_fence() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+__device__ __forceinline__ void pin(cx<double> &z) {
+    asm volatile("" : "+v"(z.x), "+v"(z.y)::"memory");
+}
+// entry r of a row for this lane's row index r, by selection; the empty asm
+// per step keeps the compiler from turning the selection into an indexed
+// load from a private copy of the row
+template <int N>
+__device__ __forceinline__ cx<double> own_entry(const Row<N> &a, int r) {
+    cx<double> v = a.e[0];
+#pragma unroll
+    for (int j = 1; j < N; j++) {
+        if (r == j) v = a.e[j];
+        asm volatile("" : "+v"(v.x), "+v"(v.y));
+    }
+    return v;
+}
+
+template <int N>
+__device__ __forceinline__ void pin_row(Row<N> &c) {
+#pragma unroll
+    for (int j = 0; j < N; j++) pin(c.e[j]);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Fill slot k with the own rows.
+template <int N>
+__device__ __forceinline__ void put(const LaneRow<N> &q, int k, const Row<N> &a) {
+    lds_fence();
+#pragma unroll
+    for (int j = 0; j < N; j++) q.s[k][q.r * N + j] = v2<double>{a.e[j].x, a.e[j].y};
+    __builtin_amdgcn_wave_barrier();
+    lds_fence();
+}
+
+template <int N>
+__device__ __forceinline__ cx<double> got(const LaneRow<N> &q, int k, int i, int j) {
+    const v2<double> v = q.s[k][i * N + j];
+    return {v.x, v.y};
+}
+
+// own row of A B, B in slot k
+template <int N>
+__device__ __forceinline__ Row<N> lmm_nn(const Row<N> &a, const LaneRow<N> &q, int k) {
+    Row<N> c = row_zero<N>();
+#pragma unroll
+    for (int m = 0; m < N; m++) {
+#pragma unroll
+        for (int j = 0; j < N; j++) c.e[j] = cmadd(c.e[j], a.e[m], got(q, k, m, j));
+        pin_row(c);   // one operand row in registers at a time
+    }
+    return c;
+}
+
+// own row of A^+ B with A in slot ka and B in slot kb: sum_m conj(A_{m r}) B_m
+template <int N>
+__device__ __forceinline__ Row<N> lmm_dn(const LaneRow<N> &q, int ka, int kb) {
+    Row<N> c = row_zero<N>();
+#pragma unroll
+    for (int m = 0; m < N; m++) {
+        const cx<double> am = got(q, ka, m, q.r);
+#pragma unroll
+        for (int j = 0; j < N; j++) c.e[j] = cmadd_cn(c.e[j], am, got(q, kb, m, j));
+        pin_row(c);
+    }
+    return c;
+}
+
+// own row of A B^+, B in slot k: sum_m A_m conj(B_{j m})
+template <int N>
+__device__ __forceinline__ Row<N> lmm_nd(const Row<N> &a, const LaneRow<N> &q, int k) {
+    Row<N> c;
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        cx<double> t = {0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < N; m++) t = cmadd_nc(t, a.e[m], got(q, k, j, m));
+        pin(t);
+        __builtin_amdgcn_sched_barrier(0);
+        c.e[j] = t;
+    }
+    return c;
+}
+
+template <int N>
+__device__ __forceinline__ double link_sum(double v, const LaneRow<N> &q) {
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; l++) s += __shfl(v, q.base + l);
+    return s;
+}
+
+template <int N>
+__device__ __forceinline__ Row<N> load_row(gptr<const v2<double>> W, int stride, int mu, int r,
+                                           int site) {
+    gptr<const v2<double>> p = W + (size_t)(mu * N * N) * stride;
+    Row<N> o;
+#pragma unroll
+    for (int j = 0; j < N; j++) o.e[j] = ld(p, row_off<N>(r, j, stride, site));
+    return o;
+}
+
+template <int N>
+__device__ __forceinline__ void store_row(gptr<v2<double>> W, int stride, int mu, int r, int site,
+                                          const Row<N> &v) {
+    gptr<v2<double>> p = W + (size_t)(mu * N * N) * stride;
+#pragma unroll
+    for (int j = 0; j < N; j++) st(p, row_off<N>(r, j, stride, site), v.e[j]);
+}
+
+template <int N>
+__device__ __forceinline__ void row_axpy(Row<N> &y, cx<double> z, const Row<N> &x) {
+#pragma unroll
+    for (int j = 0; j < N; j++) y.e[j] = cmadd(y.e[j], z, x.e[j]);
+}
+
+// own row of Omega_MU(n) = U_MU(n) S (as omega_blk); U gets the own row of
+// U_MU(n).  Upper and lower staples in two loops over nu: in one loop body the
+// compiler interleaves their loads and products and runs out of registers.
+template <int N>
+__device__ __forceinline__ Row<N> omega_row(gptr<const v2<double>> W, const CfgDesc &c,
+                                            const Geo &g, const LaneRow<N> &q, int mu,
+                                            Row<N> &U) {
+    const int st = c.stride, r = q.r;
+    Row<N> S = row_zero<N>();
+#pragma unroll 1
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        // upper: U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+, times Z^*_{mu nu}(n)
+        put(q, 1, load_row<N>(W, st, mu, r, g.i + g.up(nu)));
+        Row<N> t = lmm_nd<N>(load_row<N>(W, st, nu, r, g.i + g.up(mu)), q, 1);
+        put(q, 1, load_row<N>(W, st, nu, r, g.i));
+        t = lmm_nd<N>(t, q, 1);
+        const int k = tw_exp<N>(c, mu, nu);
+        cx<double> z = {1.0, 0.0};
+        if (k && g.n(mu) == 0 && g.n(nu) == 0) z = cconj(zphase<N>(k));
+        row_axpy(S, z, t);
+    }
+#pragma unroll 1
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        // lower: (U_mu(n-nu) U_nu(n+mu-nu))^+ U_nu(n-nu), times Z_{mu nu}(n-nu)
+        const int imn = g.i + g.dn(nu);
+        put(q, 1, load_row<N>(W, st, nu, r, imn + g.up(mu)));
+        Row<N> t = lmm_nn<N>(load_row<N>(W, st, mu, r, imn), q, 1);
+        put(q, 0, t);
+        put(q, 1, load_row<N>(W, st, nu, r, imn));
+        t = lmm_dn<N>(q, 0, 1);
+        const int k = tw_exp<N>(c, mu, nu);
+        cx<double> z = {1.0, 0.0};
+        if (k && g.n(mu) == 0 && g.back(nu) == 0) z = zphase<N>(k);
+        row_axpy(S, z, t);
+    }
+    U = load_row<N>(W, st, mu, r, g.i);
+    put(q, 1, S);
+    return lmm_nn<N>(U, q, 1);
+}
+
+// scale * P_ah(M), own row (M's rows are put in slot 0)
+template <int N>
+__device__ __forceinline__ Row<N> proj_ah_row(const Row<N> &m, const LaneRow<N> &q, double scale) {
+    put(q, 0, m);
+    Row<N> a;
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        const cx<double> mj = got(q, 0, j, q.r);           // M_{j r}
+        a.e[j] = {0.5 * (m.e[j].x - mj.x), 0.5 * (m.e[j].y + mj.y)};
+    }
+    const double t = link_sum<N>(got(q, 0, q.r, q.r).y, q) / (double)N;   // Im M_rr
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        if (j == q.r) a.e[j].y -= t;
+        a.e[j] = {scale * a.e[j].x, scale * a.e[j].y};
+    }
+    return a;
+}
+
+// exp(X), X anti-Hermitian: the scaling, degree and squarings of exp_blk; the
+// scaled argument Y stays in slot 0 for the whole Horner loop
+template <int N>
+__device__ __forceinline__ Row<N> exp_row(const Row<N> &x, const LaneRow<N> &q) {
+    double n2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; j++) n2 = fma(x.e[j].x, x.e[j].x, fma(x.e[j].y, x.e[j].y, n2));
+    const double nrm = sqrt(link_sum<N>(n2, q));
+    int s = 0;
+    if (nrm > 0.25) s = (int)ceil(log2(nrm * 4.0));
+    const double f = ldexp(1.0, -s);
+    constexpr int M = 12;
+    Row<N> y, t;
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        y.e[j] = {f * x.e[j].x, f * x.e[j].y};
+        t.e[j] = {y.e[j].x * (1.0 / M), y.e[j].y * (1.0 / M)};
+        if (j == q.r) t.e[j].x += 1.0;
+    }
+    put(q, 0, y);
+    for (int k = M - 1; k >= 1; k--) {
+        const Row<N> ty = lmm_nn<N>(t, q, 0);
+        const double ik = 1.0 / (double)k;
+#pragma unroll
+        for (int j = 0; j < N; j++) {
+            t.e[j] = {ty.e[j].x * ik, ty.e[j].y * ik};
+            if (j == q.r) t.e[j].x += 1.0;
+        }
+    }
+    for (int i = 0; i < s; i++) {
+        put(q, 1, t);
+        t = lmm_nn<N>(t, q, 1);
+    }
+    return t;
+}
+
+template <int N>
+__device__ __forceinline__ void sun_link_update_lds(const SunStageArgs &a, const CfgDesc &c,
+                                                    int site, int mu, const LaneRow<N> &q) {
+    const int in = (c.cur + 3 * a.step + a.stage) & 1;
+    gptr<const v2<double>> W = as_global<double>((const void *)(in ? c.W[1] : c.W[0]));
+    gptr<v2<double>> Wout = as_global<double>(in ? c.W[0] : c.W[1]);
+    gptr<v2<double>> X = as_global<double>(c.X);
+    const double eps = a.step < c.n_full ? a.eps : c.eps_last;
+    const Geo g = make_geo(c, site);
+    Row<N> U;
+    const Row<N> om = omega_row<N>(W, c, g, q, mu, U);
+    Row<N> z = proj_ah_row<N>(om, q, -kSunRkB[a.stage] * eps);   // B eps F, F = -P_ah(Omega)
+    if (a.stage > 0) {
+        const Row<N> xo = load_row<N>(X, c.stride, mu, q.r, site);
+        row_axpy(z, cx<double>{kSunRkA[a.stage], 0.0}, xo);
+    }
+    if (a.stage < 2) store_row<N>(X, c.stride, mu, q.r, site, z);
+    const Row<N> e = exp_row<N>(z, q);
+    put(q, 1, U);
+    store_row<N>(Wout, c.stride, mu, q.r, site, lmm_nn<N>(e, q, 1));
+}
+
+// work-group = one tile of 64 sites; wave w updates direction w for the
+// tile's sites, G at a time (lane = g N + r)
+template <int N>
+__global__ __launch_bounds__(256) void sun_stage_lds_kernel(SunStageArgs a) {
+    constexpr int G = LdsShape<N>::G, SLOT = LdsShape<N>::SLOT, LS = LdsShape<N>::LS;
+    __shared__ v2<double> lds[4][2][SLOT];
+    const int tile = blockIdx.x;
+    if (tile >= a.n_tiles) return;
+    const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ci = find_cfg(a.tile_start, a.n_act, tile);
+    const CfgDesc &c = a.cfgs[ci];   // in global memory: the twist entries are read with run-time indices
+    const int lane = threadIdx.x & 63;
+    const int g = lane / N;
+    if (g >= G) return;                      // lanes past the last whole link
+    const LaneRow<N> q{{&lds[mu][0][g * LS], &lds[mu][1][g * LS]}, lane - g * N, g * N};
+    const int first = (tile - a.tile_start[ci]) * kTile;
+#pragma unroll 1
+    for (int s0 = 0; s0 < kTile; s0 += G) {
+        const int site = first + s0 + g;
+        if (s0 + g >= kTile || site >= c.V) continue;
+        sun_link_update_lds<N>(a, c, site, mu, q);
+    }
+}
+
+// measurement: own row of G_{mu nu}(n) (as clover_blk)
+template <int N>
+__device__ __forceinline__ Row<N> clover_row(gptr<const v2<double>> W, const CfgDesc &c,
+                                             const Geo &g, const LaneRow<N> &q, int mu, int nu,
+                                             double &rp) {
+    const int st = c.stride, r = q.r;
+    const int i = g.i, ipm = g.i + g.up(mu), ipn = g.i + g.up(nu);
+    const int imm = g.i + g.dn(mu), imn = g.i + g.dn(nu);
+    Row<N> C = row_zero<N>();
+    // leaf 1: U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
+    put(q, 1, load_row<N>(W, st, nu, r, ipm));
+    Row<N> t = lmm_nn<N>(load_row<N>(W, st, mu, r, i), q, 1);
+    put(q, 1, load_row<N>(W, st, mu, r, ipn));
+    t = lmm_nd<N>(t, q, 1);
+    put(q, 1, load_row<N>(W, st, nu, r, i));
+    t = lmm_nd<N>(t, q, 1);
+    const cx<double> z = leaf_phase<N>(c, mu, nu, g.n(mu), g.n(nu));
+    row_axpy(C, z, t);
+    rp += cmul(z, own_entry<N>(t, r)).x;
+    // leaf 2: U_nu(n-nu)^+ U_mu(n-nu) U_nu(n+mu-nu) U_mu(n)^+
+    put(q, 0, load_row<N>(W, st, nu, r, imn));
+    put(q, 1, load_row<N>(W, st, mu, r, imn));
+    t = lmm_dn<N>(q, 0, 1);
+    put(q, 1, load_row<N>(W, st, nu, r, imn + g.up(mu)));
+    t = lmm_nn<N>(t, q, 1);
+    put(q, 1, load_row<N>(W, st, mu, r, i));
+    t = lmm_nd<N>(t, q, 1);
+    row_axpy(C, leaf_phase<N>(c, mu, nu, g.n(mu), g.back(nu)), t);
+    // leaf 3: U_nu(n) U_mu(n+nu-mu)^+ U_nu(n-mu)^+ U_mu(n-mu)
+    put(q, 1, load_row<N>(W, st, mu, r, ipn + g.dn(mu)));
+    t = lmm_nd<N>(load_row<N>(W, st, nu, r, i), q, 1);
+    put(q, 1, load_row<N>(W, st, nu, r, imm));
+    t = lmm_nd<N>(t, q, 1);
+    put(q, 1, load_row<N>(W, st, mu, r, imm));
+    t = lmm_nn<N>(t, q, 1);
+    row_axpy(C, leaf_phase<N>(c, mu, nu, g.back(mu), g.n(nu)), t);
+    // leaf 4: (U_nu(n-mu-nu) U_mu(n-mu))^+ U_mu(n-mu-nu) U_nu(n-nu)
+    const int imm_mn = imm + g.dn(nu);
+    put(q, 1, load_row<N>(W, st, mu, r, imm));
+    t = lmm_nn<N>(load_row<N>(W, st, nu, r, imm_mn), q, 1);
+    put(q, 0, t);
+    put(q, 1, load_row<N>(W, st, mu, r, imm_mn));
+    t = lmm_dn<N>(q, 0, 1);
+    put(q, 1, load_row<N>(W, st, nu, r, imn));
+    t = lmm_nn<N>(t, q, 1);
+    row_axpy(C, leaf_phase<N>(c, mu, nu, g.back(mu), g.back(nu)), t);
+    // G = -(i/8)(C - C^+): own row of C - C^+ is C_r - conj(column r of C)
+    put(q, 0, C);
+    Row<N> Gr;
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        const cx<double> cj = got(q, 0, j, r);             // C_{j r}
+        const double wr = C.e[j].x - cj.x, wi = C.e[j].y + cj.y;
+        Gr.e[j] = {0.125 * wi, -0.125 * wr};
+    }
+    return Gr;
+}
+
+template <int N>
+__device__ __forceinline__ double row_dot(const Row<N> &a, const Row<N> &b) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; j++) s = fma(a.e[j].x, b.e[j].x, fma(a.e[j].y, b.e[j].y, s));
+    return s;
+}
+
+// this lane's share of e(n), q(n), the plaquette sum and the action density
+// (as measure_site_n)
+template <int N>
+__device__ __forceinline__ void measure_site_lds(gptr<const v2<double>> W, const CfgDesc &c,
+                                                 const Geo &g, const LaneRow<N> &q, double v[4]) {
+    double e = 0.0, qq = 0.0, p = 0.0;
+#pragma unroll 1
+    for (int pr = 0; pr < 3; pr++) {
+        const int a1 = pr + 1;
+        const int b0 = pr == 2 ? 1 : (pr == 1 ? 1 : 2);
+        const int b1 = pr == 0 ? 3 : (pr == 1 ? 3 : 2);
+        const Row<N> Ga = clover_row<N>(W, c, g, q, 0, a1, p);
+        const Row<N> Gb = clover_row<N>(W, c, g, q, b0, b1, p);
+        e += row_dot(Ga, Ga) + row_dot(Gb, Gb);
+        const double d = row_dot(Ga, Gb);
+        qq += pr == 1 ? -d : d;
+    }
+    v[0] += e;
+    v[1] += qq * 0.025330295910584444;   // 1 / (4 pi^2)
+    v[2] += p;
+    v[3] += 6.0 - p;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void sun_measure_lds_kernel(const CfgDesc *__restrict__ cfgs,
+                                                              const int *__restrict__ tile_start,
+                                                              int n_cfg, int n_tiles,
+                                                              const MeasSlot *__restrict__ slots,
+                                                              double *__restrict__ partials,
+                                                              int buf_sel) {
+    constexpr int G = LdsShape<N>::G, SLOT = LdsShape<N>::SLOT, LS = LdsShape<N>::LS;
+    constexpr int WPB = MeasShape<N, 1>::WPB, SPW = MeasShape<N, 1>::SPW;
+    __shared__ v2<double> lds[WPB][2][SLOT];
+    __shared__ double red[4][4];
+    const int tile = blockIdx.x;
+    if (tile >= n_tiles) return;
+    const int ci = find_cfg(tile_start, n_cfg, tile);
+    if (slots[ci].row < 0) return;
+    const CfgDesc &c = cfgs[ci];     // in global memory: the twist entries are read with run-time indices
+    const int sel = buf_sel < 0 ? c.cur : ((c.cur + buf_sel) & 1);
+    gptr<const v2<double>> W = as_global<double>((const void *)(sel ? c.W[1] : c.W[0]));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane / N;
+    const int gg = g < G ? g : 0;            // lanes past the last link: no slot
+    const LaneRow<N> q{{&lds[w][0][gg * LS], &lds[w][1][gg * LS]}, lane - g * N, g * N};
+    const int first = (tile - tile_start[ci]) * kTile + SPW * w;
+    double v[4] = {0, 0, 0, 0};
+    if (g < G) {
+        for (int s0 = 0; s0 < SPW; s0 += G) {
+            const int site = first + s0 + g;
+            if (s0 + g >= SPW || site >= c.V) continue;
+            measure_site_lds<N>(W, c, make_geo(c, site), q, v);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) v[k] = wave_sum_d(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; k++) red[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const int slot = threadIdx.x >> 2, k = threadIdx.x & 3;
+        double *o = partials + ((size_t)tile * 3 + slot) * 4 + k;
+        const double t = WPB == 1 ? red[0][k]
+                       : WPB == 2 ? red[0][k] + red[1][k]
+                                  : (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+        *o = slot ? 0.0 : t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers.  The variants of each N in order (variant 0 is the default):
+// the first entry is the fastest measured on the benchmark boxes (about 10^6
+// sites of 4x4x4Nx4N, stage launch): one thread per link for N = 2..4, the
+// LDS-operand variant from N = 5 (3.1x to 8.1x the permute variants there).
+
+// Variant table: rows per lane of the permute variants, or kLds for the
+// LDS-operand variant (one row per lane).
+constexpr int kLds = 16;
+
+__host__ __device__ constexpr int sun_code(int nc, int v) {
+    // N = 2: 2, 1, LDS    3: 3, 1, LDS    4: 4, 2, 1, LDS    5, 7, 8: LDS, 1    6: LDS, 2, 1
+    return nc == 2 ? (v == 0 ? 2 : (v == 1 ? 1 : kLds))
+         : nc == 3 ? (v == 0 ? 3 : (v == 1 ? 1 : kLds))
+         : nc == 4 ? (v == 0 ? 4 : (v == 1 ? 2 : (v == 2 ? 1 : kLds)))
+         : nc == 6 ? (v == 0 ? kLds : (v == 1 ? 2 : 1))
+         : (v == 0 ? kLds : 1);
 }
 
 int sun_variant_count(int nc) {
     switch (nc) {
-        case 2: case 3: case 6: return 2;
-        case 4: return 3;
-        case 5: case 7: case 8: return 1;
+        case 2: case 3: case 6: return 3;
+        case 4: return 4;
+        case 5: case 7: case 8: return 2;
         default: return 0;
     }
 }
@@ -717,39 +1227,61 @@ int sun_variant_count(int nc) {
 int sun_rows_per_lane(int nc, int v) {
     if (v < 0) v = 0;
     if (v >= sun_variant_count(nc)) return 0;
-    return sun_rows(nc, v);
+    const int code = sun_code(nc, v);
+    return code == kLds ? 1 : code;
+}
+
+int sun_variant_lds(int nc, int v) {
+    if (v < 0) v = 0;
+    if (v >= sun_variant_count(nc)) return -1;
+    return sun_code(nc, v) == kLds ? 1 : 0;
 }
 
 template <int N, int R>
 static hipError_t stage_nr(hipStream_t s, const SunStageArgs &a) {
-    hipLaunchKernelGGL((sun_stage_kernel<N, R>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    if constexpr (R == kLds)
+        hipLaunchKernelGGL((sun_stage_lds_kernel<N>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((sun_stage_kernel<N, R>), dim3(a.n_tiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 template <int N, int R>
 static hipError_t measure_nr(hipStream_t s, const CfgDesc *cfgs, const int *tile_start, int n_cfg,
                              int n_tiles, const MeasSlot *slots, double *partials, int buf_sel) {
-    hipLaunchKernelGGL((sun_measure_kernel<N, R>), dim3(n_tiles), dim3(64 * MeasShape<N, R>::WPB), 0,
-                       s, cfgs,
-                       tile_start, n_cfg, n_tiles, slots, partials, buf_sel);
+    if constexpr (R == kLds)
+        hipLaunchKernelGGL((sun_measure_lds_kernel<N>), dim3(n_tiles),
+                           dim3(64 * MeasShape<N, 1>::WPB), 0, s, cfgs, tile_start, n_cfg, n_tiles,
+                           slots, partials, buf_sel);
+    else
+        hipLaunchKernelGGL((sun_measure_kernel<N, R>), dim3(n_tiles),
+                           dim3(64 * MeasShape<N, R>::WPB), 0, s, cfgs, tile_start, n_cfg, n_tiles,
+                           slots, partials, buf_sel);
     return hipGetLastError();
 }
 
-// F(N, R) for every (N, R) pair the variant table can name
+// F(N, R) for every (N, code) pair the variant table can name
 #define TGF_SUN_DISPATCH(F, ...)                                                  \
-    switch (nc * 16 + sun_rows_per_lane(nc, variant)) {                           \
-        case 2 * 16 + 1: return F<2, 1>(__VA_ARGS__);                             \
-        case 2 * 16 + 2: return F<2, 2>(__VA_ARGS__);                             \
-        case 3 * 16 + 1: return F<3, 1>(__VA_ARGS__);                             \
-        case 3 * 16 + 3: return F<3, 3>(__VA_ARGS__);                             \
-        case 4 * 16 + 1: return F<4, 1>(__VA_ARGS__);                             \
-        case 4 * 16 + 2: return F<4, 2>(__VA_ARGS__);                             \
-        case 4 * 16 + 4: return F<4, 4>(__VA_ARGS__);                             \
-        case 5 * 16 + 1: return F<5, 1>(__VA_ARGS__);                             \
-        case 6 * 16 + 1: return F<6, 1>(__VA_ARGS__);                             \
-        case 6 * 16 + 2: return F<6, 2>(__VA_ARGS__);                             \
-        case 7 * 16 + 1: return F<7, 1>(__VA_ARGS__);                             \
-        case 8 * 16 + 1: return F<8, 1>(__VA_ARGS__);                             \
+    switch (nc * 32 + sun_code(nc, variant < 0 ? 0 : variant)) {                  \
+        case 2 * 32 + 1: return F<2, 1>(__VA_ARGS__);                             \
+        case 2 * 32 + 2: return F<2, 2>(__VA_ARGS__);                             \
+        case 2 * 32 + kLds: return F<2, kLds>(__VA_ARGS__);                       \
+        case 3 * 32 + 1: return F<3, 1>(__VA_ARGS__);                             \
+        case 3 * 32 + 3: return F<3, 3>(__VA_ARGS__);                             \
+        case 3 * 32 + kLds: return F<3, kLds>(__VA_ARGS__);                       \
+        case 4 * 32 + 1: return F<4, 1>(__VA_ARGS__);                             \
+        case 4 * 32 + 2: return F<4, 2>(__VA_ARGS__);                             \
+        case 4 * 32 + 4: return F<4, 4>(__VA_ARGS__);                             \
+        case 4 * 32 + kLds: return F<4, kLds>(__VA_ARGS__);                       \
+        case 5 * 32 + 1: return F<5, 1>(__VA_ARGS__);                             \
+        case 5 * 32 + kLds: return F<5, kLds>(__VA_ARGS__);                       \
+        case 6 * 32 + 1: return F<6, 1>(__VA_ARGS__);                             \
+        case 6 * 32 + 2: return F<6, 2>(__VA_ARGS__);                             \
+        case 6 * 32 + kLds: return F<6, kLds>(__VA_ARGS__);                       \
+        case 7 * 32 + 1: return F<7, 1>(__VA_ARGS__);                             \
+        case 7 * 32 + kLds: return F<7, kLds>(__VA_ARGS__);                       \
+        case 8 * 32 + 1: return F<8, 1>(__VA_ARGS__);                             \
+        case 8 * 32 + kLds: return F<8, kLds>(__VA_ARGS__);                       \
         default: return hipErrorInvalidValue;                                     \
     }
 
@@ -757,6 +1289,7 @@ hipError_t launch_stage_sun(int nc, int variant, hipStream_t s, const CfgDesc *c
                             const int *tile_start, int n_act, int n_tiles, int step, int stage,
                             double eps) {
     if (n_tiles <= 0) return hipSuccess;
+    if (variant >= sun_variant_count(nc)) return hipErrorInvalidValue;
     const SunStageArgs a{cfgs, tile_start, n_act, n_tiles, step, stage, eps};
     TGF_SUN_DISPATCH(stage_nr, s, a)
 }
@@ -765,6 +1298,7 @@ hipError_t launch_measure_sun(int nc, int variant, hipStream_t s, const CfgDesc 
                               const int *tile_start, int n_cfg, int n_tiles, const MeasSlot *slots,
                               double *partials, int buf_sel) {
     if (n_tiles <= 0) return hipSuccess;
+    if (variant >= sun_variant_count(nc)) return hipErrorInvalidValue;
     TGF_SUN_DISPATCH(measure_nr, s, cfgs, tile_start, n_cfg, n_tiles, slots, partials, buf_sel)
 }
 

@@ -110,6 +110,7 @@ _sig = {
                              ctypes.c_size_t, _P]),
     "tgf_sun_variant_count": (_I, [_I]),
     "tgf_sun_rows_per_lane": (_I, [_I, _I]),
+    "tgf_sun_variant_lds": (_I, [_I, _I]),
     "tgf_load_links": (_st, [_P, _I, _P, ctypes.c_double]),
     "tgf_load_links_all": (_st, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double)]),
     "tgf_store_links": (_st, [_P, _I, _P]),

@@ -39,7 +39,8 @@ def _compare_rows(rows, ref, label):
 
 
 def _flow_both(N, dims_list, twists, starts, eps, t_end, meas_dt):
-    """Every stage variant (rows per lane) of SU(N) against the oracle."""
+    """Every stage variant (rows per lane, permutes or LDS operands) of SU(N)
+    against the oracle."""
     refs = []
     for k, (d, tw, s) in enumerate(zip(dims_list, twists, starts)):
         U = s.copy()
@@ -53,10 +54,11 @@ def _flow_both(N, dims_list, twists, starts, eps, t_end, meas_dt):
         f.load_all([torch.from_numpy(s.copy()).cuda() for s in starts])
         rows = f.flow(eps, t_end, meas_dt)
         rpl = tgf.tgf_sun_rows_per_lane(N, v)
+        kind = "LDS operands" if tgf.tgf_sun_variant_lds(N, v) == 1 else "permutes"
         for k, (d, tw) in enumerate(zip(dims_list, twists)):
             ref, U = refs[k]
             n = ref.shape[0]
-            _compare_rows(rows[:n, k], ref, f"SU({N}) rows/lane {rpl} {d} twist {tw[0]}")
+            _compare_rows(rows[:n, k], ref, f"SU({N}) rows/lane {rpl} ({kind}) {d} twist {tw[0]}")
             got = f.store(k).cpu().numpy()
             dl = np.abs(got - U).max()
             print(f"    final links max |dU| {dl:.3g}", flush=True)
@@ -66,7 +68,7 @@ def _flow_both(N, dims_list, twists, starts, eps, t_end, meas_dt):
     return [U for _, U in refs]
 
 
-@pytest.mark.parametrize("N,k", [(2, 1), (3, 1), (4, 1), (4, 3), (5, 2), (6, 1), (8, 3)])
+@pytest.mark.parametrize("N,k", [(2, 1), (3, 1), (4, 1), (4, 3), (5, 2), (6, 1), (7, 3), (8, 3)])
 def test_sun_flow_matches_oracle(N, k):
     """The TGF geometry l^2 x (N l)^2 with l = 2 (l = 4 for N = 2), the short
     plane twisted by k; near-identity links; 5 steps plus a short one."""
@@ -76,7 +78,7 @@ def test_sun_flow_matches_oracle(N, k):
     _flow_both(N, [d], [(k, 0, 0, 0, 0, 0)], [s], 0.02, 0.11, 0.04)
 
 
-@pytest.mark.parametrize("N", [3, 4])
+@pytest.mark.parametrize("N", [3, 4, 6])
 def test_sun_hot_start_and_ragged(N):
     """Haar starts, a ragged box (V not a multiple of 64) and several twisted
     planes, in one batch."""
