@@ -179,6 +179,19 @@ __device__ __forceinline__ Blk<N, R> mm_dn(const Blk<N, R> &a, const Blk<N, R> &
     return c;
 }
 
+// The rows of S taken through an empty asm statement: what computes them is
+// done before it, and no load or store moves across it.  Used as a fence
+// between staples, so that the compiler does not load the links of later
+// staples while earlier ones are still being formed.
+template <int N, int R>
+__device__ __forceinline__ void pin_blk(Blk<N, R> &S) {
+#pragma unroll
+    for (int i = 0; i < R; i++)
+#pragma unroll
+        for (int j = 0; j < N; j++) asm volatile("" : "+v"(S.e[i][j].x), "+v"(S.e[i][j].y)::"memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 template <int N, int R>
 __device__ __forceinline__ void blk_axpy(Blk<N, R> &y, cx<double> z, const Blk<N, R> &x) {
 #pragma unroll
@@ -341,6 +354,7 @@ __device__ __forceinline__ Blk<N, R> omega_blk(gptr<const v2<double>> W, const C
         cx<double> z = {1.0, 0.0};
         if (k && g.n(MU) == 0 && g.n(nu) == 0) z = cconj(zphase<N>(k));
         blk_axpy(S, z, t);
+        pin_blk(S);
         // lower: (U_mu(n-nu) U_nu(n+mu-nu))^+ U_nu(n-nu)
         const int imn = g.i + g.dn(nu);
         t = mm_nn<N, R>(load_blk<N, R>(W, st, MU, gr, imn),
@@ -349,6 +363,7 @@ __device__ __forceinline__ Blk<N, R> omega_blk(gptr<const v2<double>> W, const C
         z = {1.0, 0.0};
         if (k && g.n(MU) == 0 && g.back(nu) == 0) z = zphase<N>(k);
         blk_axpy(S, z, t);
+        pin_blk(S);
     };
     if constexpr ((N == 3 && R == 1) || (N == 2 && R == 2)) {
 #pragma unroll
@@ -517,6 +532,7 @@ __device__ __forceinline__ Blk<N, R> clover_blk(gptr<const v2<double>> W, const 
     t = mm_nd<N, R>(t, load_blk<N, R>(W, st, nu, gr, i), gr);
     const cx<double> z = leaf_phase<N>(c, mu, nu, g.n(mu), g.n(nu));
     blk_axpy(C, z, t);
+    pin_blk(C);
 #pragma unroll
     for (int r = 0; r < R; r++) rp += cmul(z, pick<N>(t.e[r], row_index<N, R>(gr, r))).x;
     // leaf 2: U_nu(n-nu)^+ U_mu(n-nu) U_nu(n+mu-nu) U_mu(n)^+
@@ -524,17 +540,20 @@ __device__ __forceinline__ Blk<N, R> clover_blk(gptr<const v2<double>> W, const 
     t = mm_nn<N, R>(t, load_blk<N, R>(W, st, nu, gr, imn + g.up(mu)), gr);
     t = mm_nd<N, R>(t, load_blk<N, R>(W, st, mu, gr, i), gr);
     blk_axpy(C, leaf_phase<N>(c, mu, nu, g.n(mu), g.back(nu)), t);
+    pin_blk(C);
     // leaf 3: U_nu(n) U_mu(n+nu-mu)^+ U_nu(n-mu)^+ U_mu(n-mu)
     t = mm_nd<N, R>(load_blk<N, R>(W, st, nu, gr, i), load_blk<N, R>(W, st, mu, gr, ipn + g.dn(mu)), gr);
     t = mm_nd<N, R>(t, load_blk<N, R>(W, st, nu, gr, imm), gr);
     t = mm_nn<N, R>(t, load_blk<N, R>(W, st, mu, gr, imm), gr);
     blk_axpy(C, leaf_phase<N>(c, mu, nu, g.back(mu), g.n(nu)), t);
+    pin_blk(C);
     // leaf 4: (U_nu(n-mu-nu) U_mu(n-mu))^+ U_mu(n-mu-nu) U_nu(n-nu)
     const int imm_mn = imm + g.dn(nu);
     t = mm_nn<N, R>(load_blk<N, R>(W, st, nu, gr, imm_mn), load_blk<N, R>(W, st, mu, gr, imm), gr);
     t = mm_dn<N, R>(t, load_blk<N, R>(W, st, mu, gr, imm_mn), gr);
     t = mm_nn<N, R>(t, load_blk<N, R>(W, st, nu, gr, imn), gr);
     blk_axpy(C, leaf_phase<N>(c, mu, nu, g.back(mu), g.back(nu)), t);
+    pin_blk(C);
     // G = -(i/8)(C - C^+): own rows of C - C^+ are C_i - conj(column i of C)
     const Blk<N, R> col = column<N, R>(C, gr);
     Blk<N, R> G;
@@ -1078,6 +1097,7 @@ __device__ __forceinline__ Row<N> clover_row(gptr<const v2<double>> W, const Cfg
     t = lmm_nd<N>(t, q, 1);
     const cx<double> z = leaf_phase<N>(c, mu, nu, g.n(mu), g.n(nu));
     row_axpy(C, z, t);
+    pin_row(C);
     rp += cmul(z, own_entry<N>(t, r)).x;
     // leaf 2: U_nu(n-nu)^+ U_mu(n-nu) U_nu(n+mu-nu) U_mu(n)^+
     put(q, 0, load_row<N>(W, st, nu, r, imn));
@@ -1088,6 +1108,7 @@ __device__ __forceinline__ Row<N> clover_row(gptr<const v2<double>> W, const Cfg
     put(q, 1, load_row<N>(W, st, mu, r, i));
     t = lmm_nd<N>(t, q, 1);
     row_axpy(C, leaf_phase<N>(c, mu, nu, g.n(mu), g.back(nu)), t);
+    pin_row(C);
     // leaf 3: U_nu(n) U_mu(n+nu-mu)^+ U_nu(n-mu)^+ U_mu(n-mu)
     put(q, 1, load_row<N>(W, st, mu, r, ipn + g.dn(mu)));
     t = lmm_nd<N>(load_row<N>(W, st, nu, r, i), q, 1);
@@ -1096,6 +1117,7 @@ __device__ __forceinline__ Row<N> clover_row(gptr<const v2<double>> W, const Cfg
     put(q, 1, load_row<N>(W, st, mu, r, imm));
     t = lmm_nn<N>(t, q, 1);
     row_axpy(C, leaf_phase<N>(c, mu, nu, g.back(mu), g.n(nu)), t);
+    pin_row(C);
     // leaf 4: (U_nu(n-mu-nu) U_mu(n-mu))^+ U_mu(n-mu-nu) U_nu(n-nu)
     const int imm_mn = imm + g.dn(nu);
     put(q, 1, load_row<N>(W, st, mu, r, imm));
@@ -1106,6 +1128,7 @@ __device__ __forceinline__ Row<N> clover_row(gptr<const v2<double>> W, const Cfg
     put(q, 1, load_row<N>(W, st, nu, r, imn));
     t = lmm_nn<N>(t, q, 1);
     row_axpy(C, leaf_phase<N>(c, mu, nu, g.back(mu), g.back(nu)), t);
+    pin_row(C);
     // G = -(i/8)(C - C^+): own row of C - C^+ is C_r - conj(column r of C)
     put(q, 0, C);
     Row<N> Gr;
