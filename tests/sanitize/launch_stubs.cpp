@@ -48,6 +48,7 @@ hipError_t launch_mc(hipStream_t, const CfgDesc *, const int *, int, int, int, i
 }
 int sun_variant_count(int nc) { return nc >= 2 && nc <= 8 ? 2 : 0; }
 int sun_rows_per_lane(int nc, int v) { return (nc >= 2 && nc <= 8 && v >= -1 && v < 2) ? nc : 0; }
+int sun_variant_lds(int nc, int v) { return (nc >= 2 && nc <= 8 && v >= -1 && v < 2) ? (v == 1) : -1; }
 hipError_t launch_stage_sun(int, int, hipStream_t, const CfgDesc *, const int *, int, int, int,
                             int, double) {
     return hipErrorNoDevice;
