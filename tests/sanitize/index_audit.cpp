@@ -269,7 +269,7 @@ static void order_check() {
         for (int d2 : {8, 24, 40, 96, 144})
             for (int d3 : {2, 5, 96}) {
                 const int d[4] = {d0, d0, d2, d3};
-                for (int blk : {kBlock, default_blk(d)}) {
+                for (int blk : {kBlock, default_blk(d), 64, 128, 192, 200}) {
                     CfgDesc c{};
                     for (int m = 0; m < 4; m++) c.d[m] = d[m];
                     c.V = d0 * d0 * d2 * d3;
