@@ -112,7 +112,8 @@ def su3_haar(n, seed, device="cpu", generator=None):
 
 
 def haar(dims, seed, device="cpu", chunk=1 << 22):
-    """Haar-random SU(3) hot start."""
+    """Haar-random SU(3) hot start.  Each chunk of `chunk` links draws its own
+    normals, so the links depend on (seed, chunk, device)."""
     shape = lattice_shape(dims) + (4,)
     n = math.prod(shape)
     g = _gen(seed, device)
