@@ -780,8 +780,8 @@ __global__ __launch_bounds__(64) void sun_check_kernel(const void *__restrict__ 
 // registers.  Each wave owns two slots of G padded link matrices (one complex
 // of padding per link puts the G links of a read in different banks).  LDS
 // operations of a wave execute in order, so a slot written by a wave is read
-// by the same wave without a barrier, and the wave barriers only keep the
-// compiler from moving accesses across a fill.
+// by the same wave without a barrier; the fences below only keep the compiler
+// from moving accesses and arithmetic across a fill or a row of a product.
 
 template <int N>
 struct LdsShape {
