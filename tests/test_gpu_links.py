@@ -126,7 +126,7 @@ def test_links_column_launch_order(storage):
 def test_large_box_one_step_vs_oracle():
     """The 32x32x96x96 Haar box of the benchmark's large leg (9.4M sites,
     column launch order, site_lds_xcd): one RK3 step, every link entry of
-    the FP64 and the FP32 12-real flows against the oracle's step."""
+    the FP64, FP32 full and FP32 12-real flows against the oracle's step."""
     dims = (32, 32, 96, 96)
     U = gen.haar(dims, seed=5, device="cuda")
     ref = U.cpu().numpy().copy()
@@ -134,7 +134,7 @@ def test_large_box_one_step_vs_oracle():
     oracle.rk3_step(ref, dims, 0.01)
     ref_dev = torch.from_numpy(ref).cuda()
     del ref
-    for storage in ("f64", "f32c12"):
+    for storage in ("f64", "f32", "f32c12"):
         f = tgf.Flow([dims], storage)
         f.set_variant(variant_index("site_lds_xcd"))
         f.load(0, U)
