@@ -939,6 +939,89 @@ __global__ __launch_bounds__(256) void check_kernel(const void *__restrict__ src
     }
 }
 
+// Batched ingest: one launch checks, and one packs, the canonical links of
+// every configuration of a load call (srcs[k] is configuration k's input; the
+// tile table numbers their tiles in order, as for a flow), instead of two
+// small launches per configuration.  The checks write per-tile defects,
+// check_batch_final_kernel reduces each configuration's tiles into out[2k],
+// out[2k+1]; the same maxima as check_kernel + check_final_kernel.
+__global__ __launch_bounds__(256) void check_batch_kernel(const double2 *const *__restrict__ srcs,
+                                                          const CfgDesc *__restrict__ cfgs,
+                                                          const int *__restrict__ tile_start,
+                                                          int n_cfg, int n_tiles,
+                                                          double *__restrict__ partials) {
+    const int tile = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= n_tiles) return;                       // whole wave
+    const int ci = find_cfg(tile_start, n_cfg, tile);
+    const int V = cfgs[ci].V;
+    const int i = (tile - tile_start[ci]) * kTile + (threadIdx.x & 63);
+    double du = 0, dd = 0;
+    if (i < V) {
+        const double2 *src = srcs[ci];
+        for (int mu = 0; mu < 4; mu++) {
+            M3<double> U;
+            const double2 *q = src + ((size_t)i * 4 + mu) * 9;
+#pragma unroll
+            for (int e = 0; e < 9; e++) U.e[e / 3][e % 3] = {q[e].x, q[e].y};
+            double a, b;
+            su3_defects(U, a, b);
+            du = fmax(du, a);
+            dd = fmax(dd, b);
+        }
+    }
+    du = wave_max(du);
+    dd = wave_max(dd);
+    if ((threadIdx.x & 63) == 0) {
+        partials[(size_t)tile * 2] = du;
+        partials[(size_t)tile * 2 + 1] = dd;
+    }
+}
+
+// one work-group per configuration: the maxima over its tiles
+__global__ __launch_bounds__(256) void check_batch_final_kernel(const double *__restrict__ partials,
+                                                                const int *__restrict__ tile_start,
+                                                                double *__restrict__ out) {
+    const int k = blockIdx.x;
+    double a = 0, b = 0;
+    for (int t = tile_start[k] + (int)threadIdx.x; t < tile_start[k + 1]; t += blockDim.x) {
+        a = fmax(a, partials[(size_t)t * 2]);
+        b = fmax(b, partials[(size_t)t * 2 + 1]);
+    }
+    a = wave_max(a);
+    b = wave_max(b);
+    __shared__ double red[4][2];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[w][0] = a; red[w][1] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[2 * k] = fmax(fmax(red[0][0], red[1][0]), fmax(red[2][0], red[3][0]));
+        out[2 * k + 1] = fmax(fmax(red[0][1], red[1][1]), fmax(red[2][1], red[3][1]));
+    }
+}
+
+// work-group = four tiles of one direction (blockIdx.y): canonical links into
+// each configuration's first link buffer W[0]
+template <class R, int NE>
+__global__ __launch_bounds__(256) void pack_batch_kernel(const double2 *const *__restrict__ srcs,
+                                                         const CfgDesc *__restrict__ cfgs,
+                                                         const int *__restrict__ tile_start,
+                                                         int n_cfg, int n_tiles) {
+    const int tile = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= n_tiles) return;
+    const int ci = find_cfg(tile_start, n_cfg, tile);
+    const CfgDesc &c = cfgs[ci];
+    const int i = (tile - tile_start[ci]) * kTile + (threadIdx.x & 63);
+    if (i >= c.V) return;
+    const int mu = blockIdx.y;
+    const double2 *q = srcs[ci] + ((size_t)i * 4 + mu) * 9;
+    cx<R> *W = (cx<R> *)c.W[0];
+#pragma unroll
+    for (int e = 0; e < NE; e++) {
+        const double2 v = q[e];
+        W[entry_index<R, NE>(mu, e, c.stride, i)] = cx<R>{(R)v.x, (R)v.y};
+    }
+}
+
 __global__ __launch_bounds__(256) void check_final_kernel(const double *__restrict__ partials,
                                                           int ntiles, double *__restrict__ out) {
     double a = 0, b = 0;
@@ -1110,6 +1193,34 @@ hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_check_final(s, partials, ntiles, out);
+}
+
+hipError_t launch_ingest_batch(Prec p, bool c12, bool pack, hipStream_t s, const void *srcs,
+                               const CfgDesc *cfgs, const int *tile_start, int n_cfg, int n_tiles,
+                               double *partials, double *out) {
+    if (n_tiles <= 0) return hipSuccess;
+    const double2 *const *sp = (const double2 *const *)srcs;
+    const int nb = (n_tiles + 3) / 4;
+    if (!pack) {
+        hipLaunchKernelGGL(check_batch_kernel, dim3(nb), dim3(256), 0, s, sp, cfgs, tile_start,
+                           n_cfg, n_tiles, partials);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(check_batch_final_kernel, dim3(n_cfg), dim3(256), 0, s, partials,
+                           tile_start, out);
+        return hipGetLastError();
+    }
+    dim3 grid(nb, 4);
+    if (p == P_F64)
+        hipLaunchKernelGGL((pack_batch_kernel<double, 9>), grid, dim3(256), 0, s, sp, cfgs,
+                           tile_start, n_cfg, n_tiles);
+    else if (c12)
+        hipLaunchKernelGGL((pack_batch_kernel<float, 6>), grid, dim3(256), 0, s, sp, cfgs,
+                           tile_start, n_cfg, n_tiles);
+    else
+        hipLaunchKernelGGL((pack_batch_kernel<float, 9>), grid, dim3(256), 0, s, sp, cfgs,
+                           tile_start, n_cfg, n_tiles);
+    return hipGetLastError();
 }
 
 hipError_t launch_check_final(hipStream_t s, const double *partials, int ntiles, double *out) {

@@ -61,6 +61,14 @@ hipError_t launch_unpack(Prec p, bool c12, hipStream_t s, const void *W, void *d
 
 // Unitarity defects: max|UU^+ - 1|, max|det U - 1|.  Source is canonical
 // (canon = true) or storage.  Partials need ceil(V/64)*2 doubles; out 2 doubles.
+// Ingest of several configurations in one go (canonical inputs srcs[k], a
+// device array of n_cfg pointers; descriptors and tile table of those
+// configurations in order): pack = false checks them (defects of
+// configuration k to out[2k], out[2k+1]; partials holds 2 doubles per tile),
+// pack = true packs them into their W[0] buffers.
+hipError_t launch_ingest_batch(Prec p, bool c12, bool pack, hipStream_t s, const void *srcs,
+                               const CfgDesc *cfgs, const int *tile_start, int n_cfg, int n_tiles,
+                               double *partials, double *out);
 hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void *src, int V,
                         int stride, double *partials, double *out);
 

@@ -60,8 +60,8 @@ struct CfgHost {
 };
 
 struct Layout {
-    size_t off_desc, off_tiles, off_blocks, off_flag, off_check, off_partials, off_rows, off_meas,
-        off_cfg0;
+    size_t off_desc, off_tiles, off_blocks, off_flag, off_check, off_src, off_partials, off_rows,
+        off_meas, off_cfg0;
     size_t total;
     int total_tiles;
     std::vector<CfgHost> cfg;
@@ -164,6 +164,7 @@ Layout make_layout(int32_t n_cfg, const tgf_geom *g, tgf_storage st, int nc = 3,
     L.off_blocks = o;   o = align_up(o + sizeof(int) * (n_cfg + 1), 256);
     L.off_flag = o;     o = align_up(o + 64, 256);
     L.off_check = o;    o = align_up(o + 64, 256);
+    L.off_src = o;      o = align_up(o + sizeof(void *) * n_cfg, 256);   // batched ingest inputs
     // measurement: 4 doubles per (tile, plane pair); unitarity check: 2 per tile
     size_t partial_doubles = (size_t)tiles * 3 * 4;
     L.off_partials = o; o = align_up(o + sizeof(double) * partial_doubles, 256);
@@ -227,6 +228,7 @@ struct tgf_ctx {
     int *d_blocks() { return (int *)(ws + L.off_blocks); }
     int *d_flag() { return (int *)(ws + L.off_flag); }
     double *d_check() { return (double *)(ws + L.off_check); }
+    const void **d_src() { return (const void **)(ws + L.off_src); }
     double *d_partials() { return (double *)(ws + L.off_partials); }
     double *d_rows() { return (double *)(ws + L.off_rows); }
     MeasSlot *d_meas() { return (MeasSlot *)(ws + L.off_meas); }
@@ -545,9 +547,27 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
         if (!links[k]) return fail(TGF_E_INVAL, "links pointer is NULL");
         if (!std::isfinite(t0[k]) || t0[k] < 0) return fail(TGF_E_INVAL, "t0 must be >= 0");
     }
+    // several SU(3) configurations: one check launch and one pack launch for
+    // all of them (the inputs' pointers and the configurations' tables uploaded
+    // first); else one check and one pack launch per configuration
+    const bool batch = !c->general && cfgs.size() > 1;
+    std::vector<int> bts;
+    if (batch) {
+        tgf_status st = upload_tables(c, cfgs, nullptr, bts);   // synchronises
+        if (st) return st;
+        // staging for the pointers now and the defects read back below (no
+        // reallocation while the pointer upload may still be reading it)
+        if ((st = ensure_stage(c, sizeof(double) * 2 * cfgs.size()))) return st;
+        memcpy(c->h_stage, links, sizeof(void *) * cfgs.size());
+        HIP_TRY(hipMemcpyAsync((void *)c->d_src(), c->h_stage, sizeof(void *) * cfgs.size(),
+                               hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(launch_ingest_batch(c->prec(), c->c12(), false, c->stream, c->d_src(), c->d_desc(),
+                                    c->d_tiles(), (int)cfgs.size(), bts[cfgs.size()],
+                                    c->d_partials(), c->d_rows()));
+    }
     // check every input before touching storage: each check writes its two
     // defects to its own slot of the rows region, one readback for all
-    for (size_t k = 0; k < cfgs.size(); k++) {
+    for (size_t k = 0; k < cfgs.size() && !batch; k++) {
         const CfgHost &h = c->L.cfg[cfgs[k]];
         if (c->general)
             HIP_TRY(launch_check_sun(c->nc, true, c->stream, links[k], h.V, h.stride,
@@ -578,7 +598,11 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
                  "max|det-1| = %.3g", bad, c->nc, worst[0], worst[1]);
         return fail(TGF_E_NOT_SU3, buf);
     }
-    for (size_t k = 0; k < cfgs.size(); k++) {
+    if (batch)
+        HIP_TRY(launch_ingest_batch(c->prec(), c->c12(), true, c->stream, c->d_src(), c->d_desc(),
+                                    c->d_tiles(), (int)cfgs.size(), bts[cfgs.size()], nullptr,
+                                    nullptr));
+    for (size_t k = 0; k < cfgs.size() && !batch; k++) {
         CfgHost &h = c->L.cfg[cfgs[k]];
         if (c->general)
             HIP_TRY(launch_pack_sun(c->nc, c->stream, links[k], c->ws + h.offW[0], h.V, h.stride));

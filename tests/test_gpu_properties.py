@@ -184,6 +184,41 @@ def test_rejects_non_su3_and_nan():
     assert e.value.status == tgf.TGF_E_INVAL
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32c12"])
+def test_batch_load_checks_every_configuration(storage):
+    """Loading several configurations at once (one check launch and one pack
+    launch for all of them): a non-SU(3) or NaN link in one configuration is
+    reported with its index and leaves every configuration unloaded; a good
+    batch flows bitwise as the same configurations loaded one by one."""
+    dims_list = [(4, 4, 12, 12), (3, 5, 4, 7), (6, 6, 18, 18)]
+    Us = [torch.from_numpy(gen.near_identity(d, 0.3, seed=40 + k).numpy().copy()).cuda()
+          for k, d in enumerate(dims_list)]
+    for kind in ("scale", "nan"):
+        f = tgf.Flow(dims_list, storage)
+        bad = [u.clone() for u in Us]
+        if kind == "scale":
+            bad[1][6, 3, 4, 2, 3] *= 1.001
+        else:
+            bad[1][0, 0, 0, 0, 0, 2, 2] = float("nan")
+        with pytest.raises(tgf.TGFError) as e:
+            f.load_all(bad)
+        assert e.value.status == tgf.TGF_E_NOT_SU3
+        assert "config 1" in str(e.value)
+        with pytest.raises(tgf.TGFError) as e:
+            f.flow(0.01, 0.02)
+        assert e.value.status == tgf.TGF_E_STATE
+    a = tgf.Flow(dims_list, storage)
+    a.load_all(Us)
+    ra = a.flow(0.01, 0.05, 0.02)
+    b = tgf.Flow(dims_list, storage)
+    for k, u in enumerate(Us):
+        b.load(k, u)
+    rb = b.flow(0.01, 0.05, 0.02)
+    assert np.array_equal(ra, rb)
+    for k in range(len(dims_list)):
+        assert torch.equal(a.store(k), b.store(k))
+
+
 def test_stream_copy():
     x = torch.randn(1 << 20, device="cuda")
     y = torch.empty_like(x)
