@@ -671,6 +671,7 @@ def stage_roofline(tgf, f, cfgs, inputs, storage, variant, workload):
             "peak_nonpacked_issue": round(ALU_PEAK_TFLOPS, 1),
             "frac_of_nonpacked_issue": round(tflops / ALU_PEAK_TFLOPS, 4),
         },
+        "stage_ms_per_flow": round(tm["stage_ms"], 3),
         "measure_ms_per_flow": round(tm["measure_ms"], 3),
     }
 
