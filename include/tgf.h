@@ -76,7 +76,7 @@ typedef enum {
 } tgf_storage;
 
 typedef struct {
-    int32_t dims[4];    /* d0, d1 (twisted plane), d2, d3; each >= 2, product < 2^28 */
+    int32_t dims[4];    /* d0, d1 (twisted plane), d2, d3; each >= 2, product <= 2^28 - 256 */
     int32_t twist[6];   /* n01, n02, n03, n12, n13, n23 in {0,1,2} */
 } tgf_geom;
 

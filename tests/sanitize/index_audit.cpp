@@ -10,7 +10,11 @@
 // and the FP64 entry planes), LDS slots inside the staged block, the source
 // lanes of the in-wave plaquette reuse among the wave's active lanes, the
 // XCD block remap and the column launch order of large boxes as one-to-one
-// maps, and every site updated exactly once.
+// maps, and every site updated exactly once.  Each byte offset is also formed
+// the kernels' way, as a 32-bit unsigned lane offset ((unsigned)j * 16u, or
+// * 8u for entry 8 of the FP32 full storage) on a 64-bit plane base, and must
+// equal the 64-bit value; boxes at the runtime's site cap (2^28 - 256) are
+// audited on their first and last work-groups, where the offsets are largest.
 // The access list per lane follows site_wave_work / site_alg_work /
 // update_link_z in kernels.hip.  Built host-only with AddressSanitizer and
 // UndefinedBehaviorSanitizer by tests/test_sanitizers.py.
@@ -70,11 +74,19 @@ static Case make_case(const std::vector<std::array<int, 4>> &dims, int ne, int r
     return k;
 }
 
+// the kernels' per-lane byte offset: 32-bit unsigned, added to a 64-bit plane base
+static void check_lane_off(int ci, int j, unsigned unit) {
+    const unsigned u = (unsigned)j * unit;
+    if ((long long)u != (long long)j * unit) fail("32-bit lane offset wraps", ci, j, (long long)j * unit);
+}
+
 // byte range of a link's 16-byte units in its buffer
 static void check_link(const Case &k, int ci, int mu, int j) {
     const CfgDesc &c = k.c[ci];
     checked++;
     if (j < 0 || j >= c.V) return fail("link site", ci, j, j);
+    check_lane_off(ci, j, 16u);
+    if (k.rbytes == 4 && k.ne == 9) check_lane_off(ci, j, 8u);
     const long long wbytes = 4LL * k.ne * c.stride * 2 * k.rbytes;
     if (k.rbytes == 4) {
         const int nu = k.ne == 9 ? 4 : 3;
@@ -99,6 +111,7 @@ static void check_x(const Case &k, int ci, int mu, int i) {
     const CfgDesc &c = k.c[ci];
     checked++;
     const long long xbytes = 4LL * 4 * c.stride * 2 * k.rbytes;
+    check_lane_off(ci, i, 16u);
     for (int u = 0; u < (k.rbytes == 4 ? 2 : 4); u++) {
         const long long off = k.rbytes == 4
                                   ? (long long)(mu * 4) * c.stride * 8 + (long long)u * c.stride * 16 + (long long)i * 16
@@ -137,7 +150,11 @@ static void lane_accesses(const CfgDesc &c, int i, unsigned done, bool wave,
         }
 }
 
-static void lds_launch(const Case &k, bool xcd, bool wave_reuse) {
+// edge > 0: the block maps are still checked over the whole launch, but only
+// the work-groups whose block is among the first or last `edge` blocks of its
+// configuration are replayed, and site coverage is not tallied (boxes of
+// hundreds of millions of sites)
+static void lds_launch(const Case &k, bool xcd, bool wave_reuse, int edge = 0) {
     const int n = (int)k.c.size();
     std::vector<int> bs(n + 1, 0);
     for (int a = 0; a < n; a++) bs[a + 1] = bs[a] + (k.c[a].V + k.c[a].blk - 1) / k.c[a].blk;
@@ -145,7 +162,8 @@ static void lds_launch(const Case &k, bool xcd, bool wave_reuse) {
     const int grid = xcd ? (nb + 7) / 8 * 8 : nb;
     std::vector<int> seen(nb, 0), order_seen(nb, 0);
     std::vector<std::vector<int>> cover(n);
-    for (int a = 0; a < n; a++) cover[a].assign(k.c[a].V, 0);
+    if (!edge)
+        for (int a = 0; a < n; a++) cover[a].assign(k.c[a].V, 0);
     std::vector<Access> acc, reuse;
     for (int hb = 0; hb < grid; hb++) {
         const int b = remap_block(hb, nb, xcd ? 1 : 0);
@@ -158,6 +176,7 @@ static void lds_launch(const Case &k, bool xcd, bool wave_reuse) {
         const int ob = block_order(b - bs[ci], c);
         if (ob < 0 || ob >= bs[ci + 1] - bs[ci]) { fail("block order", ci, b, ob); continue; }
         order_seen[bs[ci] + ob]++;
+        if (edge && ob >= edge && ob < bs[ci + 1] - bs[ci] - edge) continue;
         const int base = ob * c.blk;
         const int nblk = std::min(c.blk, c.V - base);
         if (nblk < 1 || c.blk > kBlock) { fail("block size", ci, base, nblk); continue; }
@@ -212,7 +231,7 @@ static void lds_launch(const Case &k, bool xcd, bool wave_reuse) {
                     check_link(k, ci, mu, i);
                     check_x(k, ci, mu, i);
                 }
-                cover[ci][i]++;
+                if (!edge) cover[ci][i]++;
             }
         }
     }
@@ -220,6 +239,7 @@ static void lds_launch(const Case &k, bool xcd, bool wave_reuse) {
         if (seen[b] != 1) fail("block coverage", -1, b, seen[b]);
         if (order_seen[b] != 1) fail("block order coverage", -1, b, order_seen[b]);
     }
+    if (edge) return;
     for (int a = 0; a < n; a++)
         for (int i = 0; i < k.c[a].V; i++)
             if (cover[a][i] != 1) fail("site coverage", a, i, cover[a][i]);
@@ -310,6 +330,19 @@ int main() {
                     if (planes == 0) tile_launch(k, xcd);
                 }
             }
+    // the largest boxes: 8x8x1752x1752 (196M sites, replicated in the GPU
+    // maximum-size test) and two boxes just under the site cap of 2^28 - 256,
+    // one of whole 256-site planes and one of 1020-site planes
+    const std::vector<std::array<int, 4>> big = {
+        {8, 8, 1752, 1752}, {16, 16, 1024, 1023}, {30, 34, 511, 515}};
+    for (auto &d : big) {
+        const long long V = (long long)d[0] * d[1] * d[2] * d[3];
+        if (V > (1LL << 28) - 256) fail("audit box over the site cap", 0, 0, V);
+        for (int st = 0; st < 3; st++) {
+            const Case k = make_case({d}, st == 2 ? 6 : 9, st == 0 ? 8 : 4, true);
+            for (int xcd = 0; xcd < 2; xcd++) lds_launch(k, xcd, st == 2, 64);
+        }
+    }
     std::printf("index audit: %lld accesses checked, %lld violations\n", checked, bad);
     return bad ? 1 : 0;
 }

@@ -176,6 +176,22 @@ def test_variant_table():
     assert names[:2] == ["site", "link"] and len(names) == tgf.tgf_variant_count()
 
 
+def test_su3_site_cap():
+    """Sites per SU(3) configuration are capped at 2^28 - 256, so that every
+    per-lane byte offset of the kernels (16-byte units) fits in 32 bits; the
+    workspace size of a box at the cap is formed in 64 bits."""
+    at_cap = tgf.make_geoms([(16, 16, 1024, 1023)])       # 268 173 312 sites
+    over = tgf.make_geoms([(16, 16, 1024, 1024)])         # 2^28
+    for st, per_site in ((tgf.TGF_F32_C12, 512), (tgf.TGF_F32_FULL, 704), (tgf.TGF_F64_FULL, 1408)):
+        b = tgf.tgf_workspace_bytes(1, at_cap, st)
+        assert b >= 16 * 16 * 1024 * 1023 * per_site > 1 << 32
+        assert tgf.tgf_workspace_bytes(1, over, st) == 0
+    ctx = ctypes.c_void_p()
+    assert tgf.tgf_create(ctypes.byref(ctx), 1, over, tgf.TGF_F32_C12, ctypes.c_void_p(FAKE),
+                          1 << 40, None) == tgf.TGF_E_INVAL
+    assert b"too large" in tgf.tgf_last_error() and not ctx.value
+
+
 def test_sun_workspace_and_create_validation():
     g = tgf.make_geoms([((4, 4, 16, 16), (3, 0, 0, 0, 0, 0))])
     F64 = tgf.TGF_F64_FULL

@@ -90,7 +90,9 @@ def test_stage_index_audit(tmp_path):
     LDS-staged kernel on per-configuration blocks (whole planes and 256 sites)
     and the tile-based site kernels, both block orders, all three storages,
     on the 4x4x12x12 box, the benchmark's extents, ragged and degenerate
-    batches; no access may leave its buffer, LDS block or wave."""
+    batches, and the first and last work-groups of boxes up to the site cap
+    (2^28 - 256); no access may leave its buffer, LDS block or wave, and no
+    32-bit per-lane byte offset may wrap."""
     hipcc = "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
