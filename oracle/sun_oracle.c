@@ -19,7 +19,8 @@
  *   force F = -P_ah(Omega), P_ah(M) = (M - M^+)/2 - Tr(M - M^+)/(2N)
  * integrated with Luscher's RK3 scheme (explicit Z0, Z1, Z2).  Readings as in
  * the SU(3) oracle: twist site n_mu = n_nu = 0 (parameter base[]), no trace
- * subtraction in G, eps_{0123} = +1, the same step schedule.  The twist tensor
+ * subtraction in G (parity unpinned, a convention), eps_{0123} = +1, the same
+ * step schedule.  The twist tensor
  * n_{mu nu} is taken mod N.
  *
  * The exponential is scaling-and-squaring with a term-by-term Taylor sum to

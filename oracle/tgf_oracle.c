@@ -29,7 +29,8 @@
  *   - The twist site "x1 = x2 = 1" is 1-based; 0-based it is n_mu = n_nu = 0.
  *     For the relocation test the twist site is a parameter (base[]).
  *   - "- c.c." in G^cl is minus the Hermitian adjoint of the whole sum, no
- *     trace subtraction.
+ *     trace subtraction (parity unpinned: a convention both paths adopt,
+ *     which nothing outside them fixes).
  *   - E sums Tr G_{mu nu} G_{mu nu} over all ordered pairs with weight 1/2.
  *   - G~_{mu nu} = 1/2 eps_{mu nu rho sigma} G_{rho sigma}, eps_{0123} = +1.
  *   - The force is F = -P_ah(Omega) (the Lie derivative of g0^2 S_W), which

@@ -4,7 +4,9 @@
 (sec. 3.1, g0^2 S_W / 2) with whole-array shifts; ``fd_force_components``
 differentiates it numerically along the eight su(3) generators of a link, so
 the oracle's analytic force can be checked against the action it derives
-from without reusing any of its staple algebra.
+from without reusing any of its staple algebra.  The ``torus_*`` functions
+flow fields in the maximal torus of SU(N), where the flow is an ODE for the
+link angles, with a classical Runge-Kutta tableau.
 """
 
 import numpy as np
@@ -78,3 +80,75 @@ def u_strong(beta, n=256):
     tr = (z[0] + z[1] + z[2]).real
     w = vd * np.exp(beta / 3 * tr)
     return float((tr * w).sum() / w.sum() / 3)
+
+
+# ----------------------------------------------------------------------------
+# The flow on the maximal torus of SU(N): U = diag(e^{i a_1}, ..., e^{i a_N}),
+# sum_k a_k = 0.  Plaquettes are diagonal with angles phi_k, the twist factor
+# multiplies every entry by e^{i theta_P} (theta_P = 2 pi n_{mu nu} / N on the
+# twist site), and the action above is s = sum_P sum_k [1 - cos(phi_k -
+# theta_P)].  Moving U_mu(n) along the diagonal generator T = i diag(t)
+# (sum t = 0) changes s by t . g with g_k = sum_P +-sin(phi_k - theta_P); the
+# flow generator F = i diag(f) obeys tr(T F) = ds for every such T (the
+# relation between the force and the action's derivative), so
+# f = -(g - mean(g)), and the field never leaves the torus.
+
+# three-stage Runge-Kutta tableaus (c2, a31, a32, (b1, b2, b3)) of third
+# order: Luscher's scheme exp(Z0/4), exp(8/9 Z1 - 17/36 Z0),
+# exp(3/4 Z2 - 8/9 Z1 + 17/36 Z0) written as a classical method, and others
+RK3_TABLEAUS = {
+    "luscher": (1 / 4, -2 / 9, 8 / 9, (1 / 4, 0, 3 / 4)),
+    "kutta": (1 / 2, -1, 2, (1 / 6, 2 / 3, 1 / 6)),
+    "heun": (1 / 3, 0, 2 / 3, (1 / 4, 0, 3 / 4)),
+    # third order on the group as well (nodes 1/3, 3/4)
+    "group_c2_1/3": (1 / 3, -3 / 16, 15 / 16, (1 / 6, 3 / 10, 8 / 15)),
+}
+
+
+def torus_angles(dims, N, seed, scale):
+    """Uniform link angles in [-scale, scale), the last fixed by sum = 0,
+    canonical [d3, d2, d1, d0, 4, N] order."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-scale, scale, size=tuple(dims[::-1]) + (4, N - 1))
+    return np.concatenate([a, -a.sum(-1, keepdims=True)], axis=-1)
+
+
+def torus_links(ang):
+    N = ang.shape[-1]
+    U = np.zeros(ang.shape + (N,), complex)
+    for k in range(N):
+        U[..., k, k] = np.exp(1j * ang[..., k])
+    return U
+
+
+def torus_velocity(ang, dims, twist=(1, 0, 0, 0, 0, 0), base=(0, 0, 0, 0)):
+    """da/dt of every link angle (the flow of the action above on the torus)."""
+    N = ang.shape[-1]
+    back = lambda A, mu: np.roll(A, 1, axis=3 - mu)     # A(n - mu)
+    n = coords(dims)
+    g = np.zeros_like(ang)
+    p = 0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            a_mu, a_nu = ang[..., mu, :], ang[..., nu, :]
+            phi = a_mu + _shift(a_nu, mu) - _shift(a_mu, nu) - a_nu
+            theta = np.zeros(phi.shape[:-1])
+            if twist[p] % N:
+                on = (n[mu] == base[mu]) & (n[nu] == base[nu])
+                theta[on] = 2 * np.pi * (twist[p] % N) / N
+            sn = np.sin(phi - theta[..., None])
+            # U_mu(n) enters P(n) and, daggered, P(n - nu); U_nu(n) enters
+            # P(n - mu) and, daggered, P(n)
+            g[..., mu, :] += sn - back(sn, nu)
+            g[..., nu, :] += back(sn, mu) - sn
+            p += 1
+    return -(g - g.mean(-1, keepdims=True))
+
+
+def torus_rk3(ang, dims, h, twist, tableau):
+    """One step of the classical three-stage Runge-Kutta method `tableau`."""
+    c2, a31, a32, b = tableau
+    k1 = torus_velocity(ang, dims, twist)
+    k2 = torus_velocity(ang + h * c2 * k1, dims, twist)
+    k3 = torus_velocity(ang + h * (a31 * k1 + a32 * k2), dims, twist)
+    return ang + h * (b[0] * k1 + b[1] * k2 + b[2] * k3)

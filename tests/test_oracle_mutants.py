@@ -48,6 +48,18 @@ MUTANTS = [
     ("plaquette normalisation", "out[1] = p / (18.0 * V);", "out[1] = p / (9.0 * V);"),
     ("lower staple neighbour", "long ipm_mn = step(L, ipm, nu, -1);", "long ipm_mn = step(L, i, nu, -1);"),
     ("no short final step", "int has_short = (t_end - t_last) > 1e-12;", "int has_short = 0;"),
+    # another three-stage scheme of third order on the group (nodes 1/3, 3/4,
+    # weights 1/6, 3/10, 8/15): the order test and the single-mode decay pass
+    # it, only the torus reduction to Luscher's tableau tells it apart
+    ("RK3 another third-order scheme",
+     ["W[l] = m_mul(m_exp(m_scale(0.25, Z0[l])), W[l]);",
+      "mat A = m_add(m_scale(8.0 / 9.0, Z1[l]), m_scale(-17.0 / 36.0, Z0[l]));",
+      "m_scale(0.75, Z2[l]), m_scale(-8.0 / 9.0, Z1[l])),\n                      "
+      "m_scale(17.0 / 36.0, Z0[l])"],
+     ["W[l] = m_mul(m_exp(m_scale(1.0 / 3.0, Z0[l])), W[l]);",
+      "mat A = m_add(m_scale(15.0 / 16.0, Z1[l]), m_scale(-25.0 / 48.0, Z0[l]));",
+      "m_scale(8.0 / 15.0, Z2[l]), m_scale(-51.0 / 80.0, Z1[l])),\n                      "
+      "m_scale(17.0 / 48.0, Z0[l])"]),
 ]
 
 # Monte Carlo mistakes, caught by tests/test_oracle_mc.py
@@ -77,6 +89,9 @@ SUN_MUTANTS = [
      "z_axpy(n, conj(zf(L, imn, mu, nu)), &lo, &om);"),
     ("SU(N) exponential truncated", "for (int k = 1; k <= 20; k++) {", "for (int k = 1; k <= 3; k++) {"),
     ("SU(N) RK3 17/36 -> 17/9", "{-17.0 / 36.0, 8.0 / 9.0, 0}", "{-17.0 / 9.0, 8.0 / 9.0, 0}"),
+    ("SU(N) RK3 another third-order scheme",
+     "{{0.25, 0, 0}, {-17.0 / 36.0, 8.0 / 9.0, 0}, {17.0 / 36.0, -8.0 / 9.0, 0.75}}",
+     "{{1.0 / 3.0, 0, 0}, {-25.0 / 48.0, 15.0 / 16.0, 0}, {17.0 / 48.0, -51.0 / 80.0, 8.0 / 15.0}}"),
     ("SU(N) twist taken mod 3", "int t = twist6 ? ((twist6[k] % nc) + nc) % nc : 0;",
      "int t = twist6 ? ((twist6[k] % 3) + 3) % 3 : 0;"),
 ]
@@ -89,8 +104,11 @@ def _run_mutant(tmp_path, name, old, new, pins, source="tgf_oracle.c"):
     shutil.copy(os.path.join(ROOT, "pytest.ini"), tmp_path)
     src = tmp_path / "oracle" / source
     text = src.read_text()
-    assert text.count(old) >= 1, f"mutation site for '{name}' not found"
-    src.write_text(text.replace(old, new, 1))
+    olds, news = ([old], [new]) if isinstance(old, str) else (old, new)
+    for o, n in zip(olds, news):
+        assert text.count(o) >= 1, f"mutation site for '{name}' not found: {o}"
+        text = text.replace(o, n, 1)
+    src.write_text(text)
     r = subprocess.run([sys.executable, "-m", "pytest", pins, "-q", "-x",
                         "-p", "no:cacheprovider"], cwd=tmp_path, capture_output=True, text=True,
                        timeout=900)

@@ -312,6 +312,36 @@ def test_rk3_third_order():
 
 
 # ----------------------------------------------------------------------------
+# R6: which third-order scheme.  On fields in the maximal torus of SU(3) the
+# flow is an ODE for the link angles (brute.torus_velocity, from the
+# brute-force action, not from the oracle), and Luscher's scheme, exp(Z0/4),
+# exp(8/9 Z1 - 17/36 Z0), exp(3/4 Z2 - 8/9 Z1 + 17/36 Z0), is there the
+# classical three-stage Runge-Kutta method with nodes c = (0, 1/4, 2/3),
+# a21 = 1/4, a31 = -2/9, a32 = 8/9 and weights b = (1/4, 0, 3/4).  Other
+# third-order schemes share the stability polynomial and the order (so the
+# single-mode decay and the eps^3 test pass them) but not the O(eps^4) term:
+# Kutta's, Heun's, and one that is third order on the group too (nodes 1/3,
+# 3/4), must miss the oracle's step by far more than rounding.
+
+
+@pytest.mark.parametrize("dims,twist", [((3, 3, 4, 4), TW), ((2, 3, 4, 3), (1, 0, 2, 1, 0, 2)),
+                                        ((3, 3, 4, 4), NOTW)])
+def test_rk3_is_luschers_scheme_on_the_torus(dims, twist):
+    ang = brute.torus_angles(dims, 3, seed=17, scale=2.5)
+    h = 0.05
+    U = brute.torus_links(ang)
+    oracle.rk3_step(U, dims, h, twist)
+    d = {name: np.abs(U - brute.torus_links(brute.torus_rk3(ang, dims, h, twist, tab))).max()
+         for name, tab in brute.RK3_TABLEAUS.items()}
+    assert d["luscher"] < 1e-13, d
+    assert min(v for k, v in d.items() if k != "luscher") > 1e-6, d
+    # the torus velocity is the oracle's force on such a field (it never leaves the torus)
+    F = oracle.force(brute.torus_links(ang), dims, twist)
+    f = brute.torus_velocity(ang, dims, twist)
+    assert np.abs(F - np.einsum("...k,kl->...kl", 1j * f, np.eye(3))).max() < 1e-13
+
+
+# ----------------------------------------------------------------------------
 # measurement schedule
 
 def test_schedule_rows():

@@ -199,6 +199,24 @@ def test_rk3_third_order():
     assert 6 < errs[0] / errs[1] < 10 and 6 < errs[1] / errs[2] < 10
 
 
+@pytest.mark.parametrize("N,dims,twist", [(2, (2, 2, 4, 4), (1, 0, 0, 0, 0, 0)),
+                                          (4, (2, 3, 4, 3), (3, 0, 1, 2, 0, 1)),
+                                          (5, (2, 2, 3, 5), (2, 0, 0, 0, 0, 0))])
+def test_rk3_is_luschers_scheme_on_the_torus(N, dims, twist):
+    """On fields in the maximal torus of SU(N) the flow is an ODE for the link
+    angles (brute.torus_velocity, from the brute-force action), and Luscher's
+    scheme is the classical Runge-Kutta method with c = (0, 1/4, 2/3),
+    b = (1/4, 0, 3/4); other third-order schemes miss the oracle's step."""
+    ang = brute.torus_angles(dims, N, seed=23, scale=2.5)
+    h = 0.05
+    U = brute.torus_links(ang)
+    oracle.sun_rk3_step(U, dims, h, twist=twist)
+    d = {name: np.abs(U - brute.torus_links(brute.torus_rk3(ang, dims, h, twist, tab))).max()
+         for name, tab in brute.RK3_TABLEAUS.items()}
+    assert d["luscher"] < 1e-13, d
+    assert min(v for k, v in d.items() if k != "luscher") > 1e-6, d
+
+
 def test_rejects_bad_n():
     U = np.zeros((2, 2, 2, 2, 4, 9, 9), complex)
     with pytest.raises(RuntimeError):
