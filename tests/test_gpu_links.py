@@ -1,6 +1,7 @@
 """Element-wise GPU parity of the flowed links and of the per-site densities,
-the LDS-staging race check, failure injection and the reunitarisation
-schedule across calls (all through the C ABI).
+the integrator against Luscher's tableau on torus fields, the LDS-staging
+race check, failure injection and the reunitarisation schedule across calls
+(all through the C ABI).
 
 Links (sec. 3.1, the Wilson flow): the GPU's links after one RK3 step and
 after the full 4x4x12x12 flow are compared entry by entry with the oracle's
@@ -30,6 +31,7 @@ pytestmark = pytest.mark.gpu
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
+import brute                                       # noqa: E402
 import oracle                                      # noqa: E402
 from paper_2107_03747_amd import gen, tgf          # noqa: E402
 
@@ -121,6 +123,30 @@ def test_links_column_launch_order(storage):
     f.load_all([torch.from_numpy(W).cuda(), torch.from_numpy(U).cuda()])
     f.flow(0.01, 0.02, 0.0, 0)
     assert np.array_equal(f.store(1).cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32c12"])
+@pytest.mark.parametrize("twist", [tgf.PAPER_TWIST, (1, 2, 1, 2, 1, 2)])
+def test_torus_flow_is_luschers_tableau(storage, twist):
+    """The GPU integrator against a reference that does not go through the
+    oracle: on links in the maximal torus of SU(3) the flow is an ODE for the
+    angles (tests/brute.py, from the action), and Luscher's RK3 is there the
+    classical tableau c = (0, 1/4, 2/3), b = (1/4, 0, 3/4).  Two steps of 0.05
+    on a hot torus field (angles up to 2.5), 8x8 planes that fill a wave; the
+    other third-order tableaus lie 1e-5 and more away."""
+    dims, h = (8, 8, 4, 6), 0.05
+    ang = brute.torus_angles(dims, 3, seed=41, scale=2.5)
+    refs = {}
+    for name, tab in brute.RK3_TABLEAUS.items():
+        a = ang
+        for _ in range(2):
+            a = brute.torus_rk3(a, dims, h, twist, tab)
+        refs[name] = brute.torus_links(a)
+    got, _ = gpu_links(dims, storage, brute.torus_links(ang), h, 2 * h, None, twist)
+    d = {k: np.abs(got - r).max() for k, r in refs.items()}
+    say(f"  torus {storage} {twist}: " + " ".join(f"{k} {v:.3g}" for k, v in d.items()))
+    assert d["luscher"] <= (1e-13 if storage == "f64" else 3e-6)
+    assert min(v for k, v in d.items() if k != "luscher") > 1e-5
 
 
 def test_large_box_one_step_vs_oracle():
