@@ -939,41 +939,70 @@ __global__ __launch_bounds__(256) void check_kernel(const void *__restrict__ src
     }
 }
 
-// Batched ingest: one launch checks, and one packs, the canonical links of
-// every configuration of a load call (srcs[k] is configuration k's input; the
-// tile table numbers their tiles in order, as for a flow), instead of two
-// small launches per configuration.  The checks write per-tile defects,
-// check_batch_final_kernel reduces each configuration's tiles into out[2k],
-// out[2k+1]; the same maxima as check_kernel + check_final_kernel.
-__global__ __launch_bounds__(256) void check_batch_kernel(const double2 *const *__restrict__ srcs,
-                                                          const CfgDesc *__restrict__ cfgs,
-                                                          const int *__restrict__ tile_start,
-                                                          int n_cfg, int n_tiles,
-                                                          double *__restrict__ partials) {
-    const int tile = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (tile >= n_tiles) return;                       // whole wave
+// Batched ingest: one launch checks and packs the canonical links of every
+// configuration of a load call (srcs[k] is configuration k's input; the tile
+// table numbers their tiles in order, as for a flow).  A work-group takes one
+// 64-site tile.  Its input, 64 sites x 4 links x 9 complex doubles, is one
+// contiguous 36 KB range: it arrives through coalesced 16-byte loads (four
+// consecutive lanes read 64 consecutive bytes) into LDS, one pad slot after
+// every site so that the reads below spread over the banks.  Thread
+// (site, mu) then checks its link in FP64 (the defects of check_kernel) and
+// writes it, in the context's storage, into the configuration's idle buffer
+// W[cur ^ 1] with full 16-byte unit stores; the caller makes that buffer
+// current only when every link of the batch passed, so a rejected load
+// changes no stored state.  The per-tile maxima of the two defects go to
+// partials[2 tile], partials[2 tile + 1].
+template <class R, int NE>
+__global__ __launch_bounds__(256) void ingest_batch_kernel(const double2 *const *__restrict__ srcs,
+                                                           const CfgDesc *__restrict__ cfgs,
+                                                           const int *__restrict__ tile_start,
+                                                           int n_cfg, int n_tiles,
+                                                           double *__restrict__ partials) {
+    constexpr int kEnt = 36, kPad = kEnt + 1;   // complex entries per site, LDS slots per site
+    __shared__ v2<double> lds[kTile * kPad];
+    __shared__ double red[4][2];
+    const int tile = blockIdx.x;
+    if (tile >= n_tiles) return;                           // whole work-group
     const int ci = find_cfg(tile_start, n_cfg, tile);
-    const int V = cfgs[ci].V;
-    const int i = (tile - tile_start[ci]) * kTile + (threadIdx.x & 63);
-    double du = 0, dd = 0;
-    if (i < V) {
-        const double2 *src = srcs[ci];
-        for (int mu = 0; mu < 4; mu++) {
-            M3<double> U;
-            const double2 *q = src + ((size_t)i * 4 + mu) * 9;
+    const CfgDesc &c = cfgs[ci];
+    const int i0 = (tile - tile_start[ci]) * kTile;
+    const int ns = min(kTile, c.V - i0);                   // sites i0 .. i0 + ns - 1
+    gptr<const v2<double>> src = as_global<double>((const void *)srcs[ci]) + (size_t)i0 * kEnt;
+    const int n_el = ns * kEnt;
 #pragma unroll
-            for (int e = 0; e < 9; e++) U.e[e / 3][e % 3] = {q[e].x, q[e].y};
-            double a, b;
-            su3_defects(U, a, b);
-            du = fmax(du, a);
-            dd = fmax(dd, b);
+    for (int k = 0; k < kEnt * kTile / 256; k++) {
+        const int g = k * 256 + (int)threadIdx.x;
+        if (g < n_el) {
+            const int st = g / kEnt;
+            lds[st * kPad + (g - st * kEnt)] = src[g];
         }
+    }
+    __syncthreads();
+    const int site = threadIdx.x & 63, mu = threadIdx.x >> 6;
+    double du = 0, dd = 0;
+    if (site < ns) {
+        const v2<double> *q = lds + site * kPad + mu * 9;
+        M3<double> U;
+        M3<R> V;
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            const v2<double> v = q[e];
+            U.e[e / 3][e % 3] = {v.x, v.y};
+            V.e[e / 3][e % 3] = {(R)v.x, (R)v.y};
+        }
+        su3_defects(U, du, dd);
+        store_link<R, NE>(as_global<R>(c.cur ? c.W[0] : c.W[1]), c.stride, mu, i0 + site, V);
     }
     du = wave_max(du);
     dd = wave_max(dd);
     if ((threadIdx.x & 63) == 0) {
-        partials[(size_t)tile * 2] = du;
-        partials[(size_t)tile * 2 + 1] = dd;
+        red[mu][0] = du;
+        red[mu][1] = dd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[(size_t)tile * 2] = fmax(fmax(red[0][0], red[1][0]), fmax(red[2][0], red[3][0]));
+        partials[(size_t)tile * 2 + 1] = fmax(fmax(red[0][1], red[1][1]), fmax(red[2][1], red[3][1]));
     }
 }
 
@@ -996,29 +1025,6 @@ __global__ __launch_bounds__(256) void check_batch_final_kernel(const double *__
     if (threadIdx.x == 0) {
         out[2 * k] = fmax(fmax(red[0][0], red[1][0]), fmax(red[2][0], red[3][0]));
         out[2 * k + 1] = fmax(fmax(red[0][1], red[1][1]), fmax(red[2][1], red[3][1]));
-    }
-}
-
-// work-group = four tiles of one direction (blockIdx.y): canonical links into
-// each configuration's first link buffer W[0]
-template <class R, int NE>
-__global__ __launch_bounds__(256) void pack_batch_kernel(const double2 *const *__restrict__ srcs,
-                                                         const CfgDesc *__restrict__ cfgs,
-                                                         const int *__restrict__ tile_start,
-                                                         int n_cfg, int n_tiles) {
-    const int tile = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (tile >= n_tiles) return;
-    const int ci = find_cfg(tile_start, n_cfg, tile);
-    const CfgDesc &c = cfgs[ci];
-    const int i = (tile - tile_start[ci]) * kTile + (threadIdx.x & 63);
-    if (i >= c.V) return;
-    const int mu = blockIdx.y;
-    const double2 *q = srcs[ci] + ((size_t)i * 4 + mu) * 9;
-    cx<R> *W = (cx<R> *)c.W[0];
-#pragma unroll
-    for (int e = 0; e < NE; e++) {
-        const double2 v = q[e];
-        W[entry_index<R, NE>(mu, e, c.stride, i)] = cx<R>{(R)v.x, (R)v.y};
     }
 }
 
@@ -1195,31 +1201,24 @@ hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void 
     return launch_check_final(s, partials, ntiles, out);
 }
 
-hipError_t launch_ingest_batch(Prec p, bool c12, bool pack, hipStream_t s, const void *srcs,
+hipError_t launch_ingest_batch(Prec p, bool c12, hipStream_t s, const void *srcs,
                                const CfgDesc *cfgs, const int *tile_start, int n_cfg, int n_tiles,
                                double *partials, double *out) {
     if (n_tiles <= 0) return hipSuccess;
     const double2 *const *sp = (const double2 *const *)srcs;
-    const int nb = (n_tiles + 3) / 4;
-    if (!pack) {
-        hipLaunchKernelGGL(check_batch_kernel, dim3(nb), dim3(256), 0, s, sp, cfgs, tile_start,
-                           n_cfg, n_tiles, partials);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(check_batch_final_kernel, dim3(n_cfg), dim3(256), 0, s, partials,
-                           tile_start, out);
-        return hipGetLastError();
-    }
-    dim3 grid(nb, 4);
     if (p == P_F64)
-        hipLaunchKernelGGL((pack_batch_kernel<double, 9>), grid, dim3(256), 0, s, sp, cfgs,
-                           tile_start, n_cfg, n_tiles);
+        hipLaunchKernelGGL((ingest_batch_kernel<double, 9>), dim3(n_tiles), dim3(256), 0, s, sp,
+                           cfgs, tile_start, n_cfg, n_tiles, partials);
     else if (c12)
-        hipLaunchKernelGGL((pack_batch_kernel<float, 6>), grid, dim3(256), 0, s, sp, cfgs,
-                           tile_start, n_cfg, n_tiles);
+        hipLaunchKernelGGL((ingest_batch_kernel<float, 6>), dim3(n_tiles), dim3(256), 0, s, sp,
+                           cfgs, tile_start, n_cfg, n_tiles, partials);
     else
-        hipLaunchKernelGGL((pack_batch_kernel<float, 9>), grid, dim3(256), 0, s, sp, cfgs,
-                           tile_start, n_cfg, n_tiles);
+        hipLaunchKernelGGL((ingest_batch_kernel<float, 9>), dim3(n_tiles), dim3(256), 0, s, sp,
+                           cfgs, tile_start, n_cfg, n_tiles, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(check_batch_final_kernel, dim3(n_cfg), dim3(256), 0, s, partials,
+                       tile_start, out);
     return hipGetLastError();
 }
 

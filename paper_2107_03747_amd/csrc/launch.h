@@ -63,10 +63,11 @@ hipError_t launch_unpack(Prec p, bool c12, hipStream_t s, const void *W, void *d
 // (canon = true) or storage.  Partials need ceil(V/64)*2 doubles; out 2 doubles.
 // Ingest of several configurations in one go (canonical inputs srcs[k], a
 // device array of n_cfg pointers; descriptors and tile table of those
-// configurations in order): pack = false checks them (defects of
-// configuration k to out[2k], out[2k+1]; partials holds 2 doubles per tile),
-// pack = true packs them into their W[0] buffers.
-hipError_t launch_ingest_batch(Prec p, bool c12, bool pack, hipStream_t s, const void *srcs,
+// configurations in order): checks every link (defects of configuration k
+// to out[2k], out[2k+1]; partials holds 2 doubles per tile) and packs each
+// configuration into its idle buffer W[cur ^ 1], which the caller makes
+// current when every defect is within the tolerance.
+hipError_t launch_ingest_batch(Prec p, bool c12, hipStream_t s, const void *srcs,
                                const CfgDesc *cfgs, const int *tile_start, int n_cfg, int n_tiles,
                                double *partials, double *out);
 hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void *src, int V,

@@ -547,9 +547,11 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
         if (!links[k]) return fail(TGF_E_INVAL, "links pointer is NULL");
         if (!std::isfinite(t0[k]) || t0[k] < 0) return fail(TGF_E_INVAL, "t0 must be >= 0");
     }
-    // several SU(3) configurations: one check launch and one pack launch for
-    // all of them (the inputs' pointers and the configurations' tables uploaded
-    // first); else one check and one pack launch per configuration
+    // several SU(3) configurations: one launch checks all of them and packs
+    // each into its idle buffer W[cur ^ 1] (the inputs' pointers and the
+    // configurations' tables uploaded first), which becomes current only if
+    // every link passed; else one check and, after it, one pack launch per
+    // configuration into W[0]
     const bool batch = !c->general && cfgs.size() > 1;
     std::vector<int> bts;
     if (batch) {
@@ -561,7 +563,7 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
         memcpy(c->h_stage, links, sizeof(void *) * cfgs.size());
         HIP_TRY(hipMemcpyAsync((void *)c->d_src(), c->h_stage, sizeof(void *) * cfgs.size(),
                                hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(launch_ingest_batch(c->prec(), c->c12(), false, c->stream, c->d_src(), c->d_desc(),
+        HIP_TRY(launch_ingest_batch(c->prec(), c->c12(), c->stream, c->d_src(), c->d_desc(),
                                     c->d_tiles(), (int)cfgs.size(), bts[cfgs.size()],
                                     c->d_partials(), c->d_rows()));
     }
@@ -598,10 +600,6 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
                  "max|det-1| = %.3g", bad, c->nc, worst[0], worst[1]);
         return fail(TGF_E_NOT_SU3, buf);
     }
-    if (batch)
-        HIP_TRY(launch_ingest_batch(c->prec(), c->c12(), true, c->stream, c->d_src(), c->d_desc(),
-                                    c->d_tiles(), (int)cfgs.size(), bts[cfgs.size()], nullptr,
-                                    nullptr));
     for (size_t k = 0; k < cfgs.size() && !batch; k++) {
         CfgHost &h = c->L.cfg[cfgs[k]];
         if (c->general)
@@ -613,7 +611,7 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (size_t k = 0; k < cfgs.size(); k++) {
         CfgHost &h = c->L.cfg[cfgs[k]];
-        h.cur = 0;
+        h.cur = batch ? h.cur ^ 1 : 0;
         h.t = t0[k];
         h.steps = 0;
         h.loaded = true;

@@ -31,7 +31,7 @@ hipError_t launch_check(Prec, bool, bool, hipStream_t, const void *, int, int, d
                         double *) {
     return hipErrorNoDevice;
 }
-hipError_t launch_ingest_batch(Prec, bool, bool, hipStream_t, const void *, const CfgDesc *,
+hipError_t launch_ingest_batch(Prec, bool, hipStream_t, const void *, const CfgDesc *,
                                const int *, int, int, double *, double *) {
     return hipErrorNoDevice;
 }
