@@ -845,20 +845,6 @@ __global__ __launch_bounds__(256) void finalize_kernel(const CfgDesc *__restrict
 // ingest / export / checks
 
 template <class R, int NE>
-__global__ __launch_bounds__(256) void pack_kernel(const double2 *__restrict__ src,
-                                                   cx<R> *__restrict__ W, int V, int stride) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int mu = blockIdx.y;
-    if (i >= V) return;
-    const double2 *s = src + ((size_t)i * 4 + mu) * 9;
-#pragma unroll
-    for (int e = 0; e < NE; e++) {
-        double2 v = s[e];
-        W[entry_index<R, NE>(mu, e, stride, i)] = cx<R>{(R)v.x, (R)v.y};
-    }
-}
-
-template <class R, int NE>
 __global__ __launch_bounds__(256) void unpack_kernel(const cx<R> *__restrict__ W,
                                                      double2 *__restrict__ dst, int V, int stride) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -902,7 +888,9 @@ __device__ __forceinline__ void su3_defects(const M3<double> &U, double &du, dou
     dd = finite_or_inf(sqrt((det.x - 1) * (det.x - 1) + det.y * det.y));
 }
 
-template <class R, int NE, bool CANON>
+// Unitarity defects of stored links, per tile (the canonical inputs of a
+// load are checked by ingest_batch_kernel).
+template <class R, int NE>
 __global__ __launch_bounds__(256) void check_kernel(const void *__restrict__ src, int V, int stride,
                                                     double *__restrict__ partials) {
     const int tile = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -911,19 +899,13 @@ __global__ __launch_bounds__(256) void check_kernel(const void *__restrict__ src
     if (i < V) {
         for (int mu = 0; mu < 4; mu++) {
             M3<double> U;
-            if constexpr (CANON) {
-                const double2 *s = (const double2 *)src + ((size_t)i * 4 + mu) * 9;
+            const cx<R> *q = (const cx<R> *)src;
 #pragma unroll
-                for (int e = 0; e < 9; e++) U.e[e / 3][e % 3] = {s[e].x, s[e].y};
-            } else {
-                const cx<R> *q = (const cx<R> *)src;
-#pragma unroll
-                for (int e = 0; e < NE; e++) {
-                    cx<R> v = q[entry_index<R, NE>(mu, e, stride, i)];
-                    U.e[e / 3][e % 3] = {(double)v.x, (double)v.y};
-                }
-                if constexpr (NE == 6) rebuild_row2(U);
+            for (int e = 0; e < NE; e++) {
+                cx<R> v = q[entry_index<R, NE>(mu, e, stride, i)];
+                U.e[e / 3][e % 3] = {(double)v.x, (double)v.y};
             }
+            if constexpr (NE == 6) rebuild_row2(U);
             double a, b;
             su3_defects(U, a, b);
             du = fmax(du, a);
@@ -1148,22 +1130,6 @@ hipError_t launch_finalize(hipStream_t s, const CfgDesc *cfgs, const int *tile_s
     return hipGetLastError();
 }
 
-hipError_t launch_pack(Prec p, bool c12, hipStream_t s, const void *src, void *W, int V,
-                       int stride) {
-    dim3 grid((V + 255) / 256, 4);
-    const double2 *in = (const double2 *)src;
-    if (p == P_F64)
-        hipLaunchKernelGGL((pack_kernel<double, 9>), grid, dim3(256), 0, s, in,
-                           (cx<double> *)W, V, stride);
-    else if (c12)
-        hipLaunchKernelGGL((pack_kernel<float, 6>), grid, dim3(256), 0, s, in, (cx<float> *)W,
-                           V, stride);
-    else
-        hipLaunchKernelGGL((pack_kernel<float, 9>), grid, dim3(256), 0, s, in, (cx<float> *)W,
-                           V, stride);
-    return hipGetLastError();
-}
-
 hipError_t launch_unpack(Prec p, bool c12, hipStream_t s, const void *W, void *dst, int V,
                          int stride) {
     dim3 grid((V + 255) / 256, 4);
@@ -1180,22 +1146,19 @@ hipError_t launch_unpack(Prec p, bool c12, hipStream_t s, const void *W, void *d
     return hipGetLastError();
 }
 
-hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void *src, int V,
-                        int stride, double *partials, double *out) {
+hipError_t launch_check(Prec p, bool c12, hipStream_t s, const void *src, int V, int stride,
+                        double *partials, double *out) {
     const int ntiles = (V + kTile - 1) / kTile;
     dim3 grid((ntiles + 3) / 4);
-    if (canon)
-        hipLaunchKernelGGL((check_kernel<double, 9, true>), grid, dim3(256), 0, s, src, V, stride,
+    if (p == P_F64)
+        hipLaunchKernelGGL((check_kernel<double, 9>), grid, dim3(256), 0, s, src, V, stride,
                            partials);
-    else if (p == P_F64)
-        hipLaunchKernelGGL((check_kernel<double, 9, false>), grid, dim3(256), 0, s, src, V,
-                           stride, partials);
     else if (c12)
-        hipLaunchKernelGGL((check_kernel<float, 6, false>), grid, dim3(256), 0, s, src, V,
-                           stride, partials);
+        hipLaunchKernelGGL((check_kernel<float, 6>), grid, dim3(256), 0, s, src, V, stride,
+                           partials);
     else
-        hipLaunchKernelGGL((check_kernel<float, 9, false>), grid, dim3(256), 0, s, src, V,
-                           stride, partials);
+        hipLaunchKernelGGL((check_kernel<float, 9>), grid, dim3(256), 0, s, src, V, stride,
+                           partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_check_final(s, partials, ntiles, out);

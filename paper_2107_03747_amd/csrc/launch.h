@@ -53,25 +53,24 @@ hipError_t launch_finalize(hipStream_t s, const CfgDesc *cfgs, const int *tile_s
                            const MeasSlot *slots, const double *partials, double *rows,
                            int n_cfg_total, int *flag, int nc);
 
-// canonical complex128 [V][4][3][3] <-> storage buffer W (of config c)
-hipError_t launch_pack(Prec p, bool c12, hipStream_t s, const void *src, void *W, int V,
-                       int stride);
+// storage buffer W (of config c) -> canonical complex128 [V][4][3][3]
 hipError_t launch_unpack(Prec p, bool c12, hipStream_t s, const void *W, void *dst, int V,
                          int stride);
 
-// Unitarity defects: max|UU^+ - 1|, max|det U - 1|.  Source is canonical
-// (canon = true) or storage.  Partials need ceil(V/64)*2 doubles; out 2 doubles.
-// Ingest of several configurations in one go (canonical inputs srcs[k], a
-// device array of n_cfg pointers; descriptors and tile table of those
-// configurations in order): checks every link (defects of configuration k
-// to out[2k], out[2k+1]; partials holds 2 doubles per tile) and packs each
-// configuration into its idle buffer W[cur ^ 1], which the caller makes
-// current when every defect is within the tolerance.
+// Ingest of one or more configurations in one go (canonical complex128
+// inputs srcs[k], a device array of n_cfg pointers; descriptors and tile
+// table of those configurations in order): checks every link (unitarity
+// defects max|UU^+ - 1|, max|det U - 1| of configuration k to out[2k],
+// out[2k+1]; partials holds 2 doubles per tile) and packs each configuration
+// into its idle buffer W[cur ^ 1], which the caller makes current when every
+// defect is within the tolerance.
 hipError_t launch_ingest_batch(Prec p, bool c12, hipStream_t s, const void *srcs,
                                const CfgDesc *cfgs, const int *tile_start, int n_cfg, int n_tiles,
                                double *partials, double *out);
-hipError_t launch_check(Prec p, bool c12, bool canon, hipStream_t s, const void *src, int V,
-                        int stride, double *partials, double *out);
+// Unitarity defects of stored links.  Partials need ceil(V/64)*2 doubles;
+// out 2 doubles.
+hipError_t launch_check(Prec p, bool c12, hipStream_t s, const void *src, int V, int stride,
+                        double *partials, double *out);
 
 // Topological charge per slice of direction `dir` for config ci (exec-order
 // descriptor at cfgs[ci]); partials need n_slices * ceil(slice_sites/1024)

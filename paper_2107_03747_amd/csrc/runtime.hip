@@ -398,15 +398,15 @@ tgf_status check_cfg(tgf_ctx *c, int32_t cfg) {
     return TGF_OK;
 }
 
-// Unitarity defects of canonical (canon) or stored links of config cfg.
-tgf_status run_check(tgf_ctx *c, int cfg, const void *src, bool canon, double out[2]) {
+// Unitarity defects of the stored links of config cfg.
+tgf_status run_check(tgf_ctx *c, int cfg, const void *src, double out[2]) {
     const CfgHost &h = c->L.cfg[cfg];
     if (c->general)
-        HIP_TRY(launch_check_sun(c->nc, canon, c->stream, src, h.V, h.stride, c->d_partials(),
+        HIP_TRY(launch_check_sun(c->nc, false, c->stream, src, h.V, h.stride, c->d_partials(),
                                  c->d_check()));
     else
-        HIP_TRY(launch_check(c->prec(), c->c12(), canon, c->stream, src, h.V, h.stride,
-                             c->d_partials(), c->d_check()));
+        HIP_TRY(launch_check(c->prec(), c->c12(), c->stream, src, h.V, h.stride, c->d_partials(),
+                             c->d_check()));
     tgf_status st = ensure_stage(c, 64);
     if (st) return st;
     HIP_TRY(hipMemcpyAsync(c->h_stage, c->d_check(), 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -547,12 +547,12 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
         if (!links[k]) return fail(TGF_E_INVAL, "links pointer is NULL");
         if (!std::isfinite(t0[k]) || t0[k] < 0) return fail(TGF_E_INVAL, "t0 must be >= 0");
     }
-    // several SU(3) configurations: one launch checks all of them and packs
-    // each into its idle buffer W[cur ^ 1] (the inputs' pointers and the
+    // SU(3): one launch checks every configuration of the call and packs each
+    // into its idle buffer W[cur ^ 1] (the inputs' pointers and the
     // configurations' tables uploaded first), which becomes current only if
-    // every link passed; else one check and, after it, one pack launch per
-    // configuration into W[0]
-    const bool batch = !c->general && cfgs.size() > 1;
+    // every link passed; SU(N): one check launch per configuration, then,
+    // when all passed, one pack launch each into W[0]
+    const bool batch = !c->general;
     std::vector<int> bts;
     if (batch) {
         tgf_status st = upload_tables(c, cfgs, nullptr, bts);   // synchronises
@@ -571,11 +571,7 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
     // defects to its own slot of the rows region, one readback for all
     for (size_t k = 0; k < cfgs.size() && !batch; k++) {
         const CfgHost &h = c->L.cfg[cfgs[k]];
-        if (c->general)
-            HIP_TRY(launch_check_sun(c->nc, true, c->stream, links[k], h.V, h.stride,
-                                     c->d_partials(), c->d_rows() + 2 * k));
-        else
-            HIP_TRY(launch_check(c->prec(), c->c12(), true, c->stream, links[k], h.V, h.stride,
+        HIP_TRY(launch_check_sun(c->nc, true, c->stream, links[k], h.V, h.stride,
                                  c->d_partials(), c->d_rows() + 2 * k));
     }
     tgf_status st0 = ensure_stage(c, sizeof(double) * 2 * cfgs.size());
@@ -602,11 +598,7 @@ static tgf_status load_impl(tgf_ctx *c, const std::vector<int> &cfgs,
     }
     for (size_t k = 0; k < cfgs.size() && !batch; k++) {
         CfgHost &h = c->L.cfg[cfgs[k]];
-        if (c->general)
-            HIP_TRY(launch_pack_sun(c->nc, c->stream, links[k], c->ws + h.offW[0], h.V, h.stride));
-        else
-            HIP_TRY(launch_pack(c->prec(), c->c12(), c->stream, links[k], c->ws + h.offW[0], h.V,
-                                h.stride));
+        HIP_TRY(launch_pack_sun(c->nc, c->stream, links[k], c->ws + h.offW[0], h.V, h.stride));
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (size_t k = 0; k < cfgs.size(); k++) {
@@ -704,7 +696,7 @@ tgf_status tgf_unitarity(tgf_ctx *c, int32_t cfg, double *out) {
     if (!out) return fail(TGF_E_INVAL, "out is NULL");
     CfgHost &h = c->L.cfg[cfg];
     if (!h.loaded) return fail(TGF_E_STATE, "config not loaded");
-    return run_check(c, cfg, c->ws + h.offW[h.cur], false, out);
+    return run_check(c, cfg, c->ws + h.offW[h.cur], out);
 }
 
 tgf_status tgf_measure(tgf_ctx *c, tgf_obs *out_host) {

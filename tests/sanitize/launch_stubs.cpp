@@ -21,14 +21,10 @@ hipError_t launch_finalize(hipStream_t, const CfgDesc *, const int *, int, const
                            const double *, double *, int, int *, int) {
     return hipErrorNoDevice;
 }
-hipError_t launch_pack(Prec, bool, hipStream_t, const void *, void *, int, int) {
-    return hipErrorNoDevice;
-}
 hipError_t launch_unpack(Prec, bool, hipStream_t, const void *, void *, int, int) {
     return hipErrorNoDevice;
 }
-hipError_t launch_check(Prec, bool, bool, hipStream_t, const void *, int, int, double *,
-                        double *) {
+hipError_t launch_check(Prec, bool, hipStream_t, const void *, int, int, double *, double *) {
     return hipErrorNoDevice;
 }
 hipError_t launch_ingest_batch(Prec, bool, hipStream_t, const void *, const CfgDesc *,
