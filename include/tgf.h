@@ -171,11 +171,16 @@ tgf_status tgf_create_sun(tgf_ctx **out, int32_t nc, int32_t n_cfg, const tgf_ge
  * canonical device memory into the context's storage and set its flow time to
  * t0 (and its step count, which schedules reunitarisation, to 0).  The input is checked:
  * max |U U^+ - 1| and |det U - 1| above 1e-10 (or any non-finite entry)
- * return TGF_E_NOT_SU3 and leave cfg unloaded.  Synchronises. */
+ * return TGF_E_NOT_SU3 and change nothing (a configuration that was not
+ * loaded stays unloaded, a loaded one keeps its links, time and step count).
+ * Synchronises. */
 tgf_status tgf_load_links(tgf_ctx *c, int32_t cfg, const void *links_dev, double t0);
 
 /* Same for every configuration at once: links_dev[n_cfg] (host array of
- * device pointers), t0[n_cfg] (host).  One check, one synchronisation. */
+ * device pointers), t0[n_cfg] (host).  SU(3): one launch checks and packs all
+ * of them; one synchronisation.  If any link of any configuration fails the
+ * check, TGF_E_NOT_SU3 names the first such configuration and no
+ * configuration changes. */
 tgf_status tgf_load_links_all(tgf_ctx *c, const void *const *links_dev, const double *t0);
 
 /* Write the current (flowed) links of cfg, the field V_t of sec. 1, in

@@ -186,10 +186,12 @@ def test_rejects_non_su3_and_nan():
 
 @pytest.mark.parametrize("storage", ["f64", "f32c12"])
 def test_batch_load_checks_every_configuration(storage):
-    """Loading several configurations at once (one check launch and one pack
-    launch for all of them): a non-SU(3) or NaN link in one configuration is
-    reported with its index and leaves every configuration unloaded; a good
-    batch flows bitwise as the same configurations loaded one by one."""
+    """Loading several configurations at once (one launch checks and packs
+    all of them): a non-SU(3) or NaN link in one configuration is reported
+    with its index and leaves every configuration unloaded; a rejected load
+    into a context that holds flowed configurations changes nothing (its
+    flow continues bitwise as if the load had not been tried); a good batch
+    flows bitwise as the same configurations loaded one by one."""
     dims_list = [(4, 4, 12, 12), (3, 5, 4, 7), (6, 6, 18, 18)]
     Us = [torch.from_numpy(gen.near_identity(d, 0.3, seed=40 + k).numpy().copy()).cuda()
           for k, d in enumerate(dims_list)]
@@ -215,6 +217,20 @@ def test_batch_load_checks_every_configuration(storage):
         b.load(k, u)
     rb = b.flow(0.01, 0.05, 0.02)
     assert np.array_equal(ra, rb)
+    for k in range(len(dims_list)):
+        assert torch.equal(a.store(k), b.store(k))
+    # a rejected load changes nothing: a continues like b
+    held = [a.store(k).clone() for k in range(len(dims_list))]
+    t_held = [a.time(k) for k in range(len(dims_list))]
+    with pytest.raises(tgf.TGFError) as e:
+        a.load_all(bad)
+    assert e.value.status == tgf.TGF_E_NOT_SU3
+    with pytest.raises(tgf.TGFError) as e:
+        a.load(1, bad[1])
+    assert e.value.status == tgf.TGF_E_NOT_SU3
+    for k in range(len(dims_list)):
+        assert torch.equal(a.store(k), held[k]) and a.time(k) == t_held[k]
+    assert np.array_equal(a.flow(0.01, 0.09, 0.02), b.flow(0.01, 0.09, 0.02))
     for k in range(len(dims_list)):
         assert torch.equal(a.store(k), b.store(k))
 
