@@ -717,16 +717,18 @@ __global__ __launch_bounds__(192) void measure_kernel(const CfgDesc *__restrict_
     const int ci = find_cfg(tile_start, n_cfg, tile);
     if (slots[ci].row < 0) return;
     const CfgDesc c = cfgs[ci];
-    const int i = (tile - tile_start[ci]) * kTile + (threadIdx.x & 63);
+    const int tb = (tile - tile_start[ci]) * kTile;            // site of lane 0
+    const int i = tb + (threadIdx.x & 63);
     double v[4] = {0, 0, 0, 0};
     if (i < c.V) {
         const int sel = buf_sel < 0 ? c.cur : ((c.cur + buf_sel) & 1);
         const Links<R, NE> W{as_global<R>((const void *)(sel ? c.W[1] : c.W[0])), c.stride};
         const Geo g = make_geo(c, i);
+        const int nw = min(kTile, c.V - tb);
         switch (pair) {
-            case 0: measure_pair<R, 0>(W, c, g, v); break;
-            case 1: measure_pair<R, 1>(W, c, g, v); break;
-            default: measure_pair<R, 2>(W, c, g, v); break;
+            case 0: measure_pair<R, 0>(W, c, g, v, tb, nw); break;
+            case 1: measure_pair<R, 1>(W, c, g, v, tb, nw); break;
+            default: measure_pair<R, 2>(W, c, g, v, tb, nw); break;
         }
     }
 #pragma unroll
@@ -746,7 +748,7 @@ template <class R, int NE>
 __global__ __launch_bounds__(256) void slice_charge_kernel(const CfgDesc *__restrict__ cfgs, int ci,
                                                            int dir, int chunk_sites,
                                                            double *__restrict__ partials) {
-    const CfgDesc c = cfgs[ci];
+    const CfgDesc &c = cfgs[ci];   // read in place (c.d is indexed at run time)
     const int s = blockIdx.y;
     const int dd = c.d[dir];
     const int S = c.V / dd;
@@ -754,24 +756,31 @@ __global__ __launch_bounds__(256) void slice_charge_kernel(const CfgDesc *__rest
     const int o0 = dir == 0 ? 1 : 0;
     const int o1 = dir <= 1 ? 2 : 1;
     const int o2 = dir == 3 ? 2 : 3;
-    int st[4];
-    st[0] = 1; st[1] = c.d[0]; st[2] = c.d[0] * c.d[1]; st[3] = st[2] * c.d[2];
-    const int sa = st[o0], sb = st[o1], sc = st[o2], sd = st[dir];
+    // site stride of direction m (no private array indexed at run time)
+    auto stride_of = [&](int m) {
+        return m == 0 ? 1 : m == 1 ? c.d[0] : m == 2 ? c.d[0] * c.d[1] : c.d[0] * c.d[1] * c.d[2];
+    };
+    const int sa = stride_of(o0), sb = stride_of(o1), sc = stride_of(o2), sd = stride_of(dir);
     const int da = c.d[o0], db = c.d[o1];
     const Links<R, NE> W{as_global<R>((const void *)(c.cur ? c.W[1] : c.W[0])), c.stride};
     double acc = 0;
     const int j0 = blockIdx.x * chunk_sites;
     const int j1 = min(j0 + chunk_sites, S);
+#pragma unroll 1
     for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) {
         const int na = j % da, r = j / da;
         const int nb = r % db, nc = r / db;
         const int i = na * sa + nb * sb + nc * sc + s * sd;
         const Geo g = make_geo(c, i);
-        double v[4];
+        double v[4];   // lanes do not hold consecutive sites: leaves formed link by link
+        // the fences keep the three plane pairs from being interleaved (without
+        // them the kernel needs every register and spills)
         measure_pair<R, 0>(W, c, g, v);
         acc += v[1];
+        __builtin_amdgcn_sched_barrier(0);
         measure_pair<R, 1>(W, c, g, v);
         acc += v[1];
+        __builtin_amdgcn_sched_barrier(0);
         measure_pair<R, 2>(W, c, g, v);
         acc += v[1];
     }
@@ -795,10 +804,11 @@ __global__ __launch_bounds__(256) void density_kernel(const CfgDesc *__restrict_
     if (i >= c.V) return;
     const Links<R, NE> W{as_global<R>((const void *)(c.cur ? c.W[1] : c.W[0])), c.stride};
     const Geo g = make_geo(c, i);
+    const int tb = i - (int)(threadIdx.x & 63), nw = min(64, c.V - tb);   // lanes = sites tb ..
     double v0[4], v1[4], v2[4];
-    measure_pair<R, 0>(W, c, g, v0);
-    measure_pair<R, 1>(W, c, g, v1);
-    measure_pair<R, 2>(W, c, g, v2);
+    measure_pair<R, 0>(W, c, g, v0, tb, nw);
+    measure_pair<R, 1>(W, c, g, v1, tb, nw);
+    measure_pair<R, 2>(W, c, g, v2, tb, nw);
     if (e_out) e_out[i] = (v0[0] + v1[0]) + v2[0];
     if (q_out) q_out[i] = (v0[1] + v1[1]) + v2[1];
 }

@@ -50,15 +50,17 @@ __global__ __launch_bounds__(192) void measure_canon_kernel(CfgDesc c, const dou
                                                             double *partials) {
     const int tile = blockIdx.x;
     const int pair = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int i = tile * kTile + (threadIdx.x & 63);
+    const int tb = tile * kTile;                               // site of lane 0
+    const int i = tb + (threadIdx.x & 63);
     double v[4] = {0, 0, 0, 0};
     if (i < c.V) {
         const CanonLinks W{links};
         const Geo g = make_geo(c, i);
+        const int nw = min(kTile, c.V - tb);
         switch (pair) {
-            case 0: measure_pair<double, 0>(W, c, g, v); break;
-            case 1: measure_pair<double, 1>(W, c, g, v); break;
-            default: measure_pair<double, 2>(W, c, g, v); break;
+            case 0: measure_pair<double, 0>(W, c, g, v, tb, nw); break;
+            case 1: measure_pair<double, 1>(W, c, g, v, tb, nw); break;
+            default: measure_pair<double, 2>(W, c, g, v, tb, nw); break;
         }
     }
 #pragma unroll
