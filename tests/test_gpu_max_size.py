@@ -21,6 +21,16 @@ Sizes: FP32 12-real on 8x8x1752x1752 (196 M sites, lane offsets up to
 storage would need 272 GB at the 2^31 crossing and is left to the host audit
 of the same offset code (tests/sanitize/index_audit.cpp), which also covers
 boxes at the site cap of 2^28 - 256.
+
+SU(N) (FP64, N^2 entry planes per direction, sites capped at 2^28 / N^2 -
+256 so that a lane's offset into a direction's planes fits in 32 bits): boxes
+just under the cap, SU(5) on 2x2x1630x1640 (10.7 M sites) and SU(8) on
+2x2x1008x1040 (4.19 M sites), whose largest offsets are 4.28e9 and 4.29e9 of
+2^32, built of copies of 2x2x10x10 and 2x2x16x16 fields; every stage variant
+(LDS operands, cross-lane permutes) flows them bitwise like the small box,
+whose step is checked against the SU(N) oracle (1e-12).  The SU(N) kernels
+take no position-dependent path (no wave votes), so every copy's arithmetic
+is that of the small box.
 """
 
 import numpy as np
@@ -113,3 +123,64 @@ def test_replicated_box_flows_like_its_copy(storage):
     assert dq.max() <= 1e-9 * n
     del links
     torch.cuda.empty_cache()
+
+
+SUN_CASES = {5: ((2, 2, 10, 10), 2, (163, 164)), 8: ((2, 2, 16, 16), 3, (63, 65))}
+
+
+@pytest.mark.parametrize("N", [5, 8])
+def test_sun_replicated_box_at_the_site_cap(N):
+    small_dims, k, (k2, k3) = SUN_CASES[N]
+    twist = (k, 0, 0, 0, 0, 0)
+    big = (small_dims[0], small_dims[1], small_dims[2] * k2, small_dims[3] * k3)
+    V = int(np.prod(big))
+    cap = (1 << 28) // (N * N) - 256
+    assert 0.99 * cap < V <= cap
+    links_bytes = V * 4 * N * N * 16
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 4 * links_bytes + (4 << 30):       # workspace (3 x links) + links
+        pytest.skip(f"needs {4 * links_bytes / 1e9:.0f} GB of device memory")
+
+    U = gen.near_identity_n(small_dims, N, 0.4, seed=70 + N)
+    ref = U.numpy().copy()
+    oracle.sun_rk3_step(ref, small_dims, 0.01, twist=twist)
+    for v in range(tgf.tgf_sun_variant_count(N)):
+        kind = "LDS operands" if tgf.tgf_sun_variant_lds(N, v) == 1 else "permutes"
+        say(f"  SU({N}) variant {v} ({kind}): small {small_dims}")
+        fs = tgf.Flow([(small_dims, twist)], "f64", nc=N)
+        fs.set_variant(v)
+        fs.load(0, U.cuda())
+        rows_s = fs.flow(0.01, 0.01, 0.01)
+        small = fs.store(0)
+        torch.cuda.synchronize()
+        d = np.abs(small.cpu().numpy() - ref).max()
+        say(f"  small vs oracle: max |dU| {d:.3g}")
+        assert d <= 1e-12
+        fs.close()
+
+        say(f"  big {big} ({V} sites, cap {cap}): load, one step, store")
+        links = U.cuda().repeat(k3, k2, 1, 1, 1, 1, 1)
+        fb = tgf.Flow([(big, twist)], "f64", nc=N)
+        fb.set_variant(v)
+        fb.load(0, links)
+        rows_b = fb.flow(0.01, 0.01, 0.01)
+        fb.store(0, out=links)
+        torch.cuda.synchronize()
+        fb.close()
+        del fb
+        torch.cuda.empty_cache()
+        bv = links.view(k3, small_dims[3], k2, small_dims[2], -1)
+        sv = small.view(small_dims[3], 1, small_dims[2], -1)
+        differing = sum(int((bv[a] != sv).any(dim=-1).sum().item()) for a in range(k3))
+        say(f"  copies: {k2 * k3}, sites differing from the small box: {differing}")
+        assert differing == 0
+        rb, rs = rows_b[:, 0], rows_s[:, 0]
+        for col in ("E", "plaq"):
+            rel = np.abs(rb[:, COL[col]] - rs[:, COL[col]]) / np.abs(rs[:, COL[col]])
+            assert rel.max() <= 1e-11, (col, rb[:, COL[col]], rs[:, COL[col]])
+        rel = np.abs(rb[:, COL["action"]] - k2 * k3 * rs[:, COL["action"]]) / np.abs(
+            k2 * k3 * rs[:, COL["action"]])
+        assert rel.max() <= 1e-11
+        del links
+        torch.cuda.empty_cache()
