@@ -741,17 +741,16 @@ __global__ __launch_bounds__(192) void measure_kernel(const CfgDesc *__restrict_
 
 // ---------------------------------------------------------------------------
 // Topological charge per slice: q(s) = (1/16 pi^2) sum_{n : n_dir = s} Tr G G~
-// (eq. qlatt restricted to one slice).  Block (chunk, s) sums chunk_sites
-// sites of slice s; the sites of a slice are enumerated over the three other
-// directions in increasing order.  FP64 partials, summed in a fixed order.
+// (eq. qlatt restricted to one slice).  Block (b, s) takes the sites
+// 256 b .. 256 b + 255 of slice s, one per thread; the sites of a slice are
+// enumerated over the three other directions in increasing order.  FP64
+// partials, summed in a fixed order.
 template <class R, int NE>
 __global__ __launch_bounds__(256) void slice_charge_kernel(const CfgDesc *__restrict__ cfgs, int ci,
-                                                           int dir, int chunk_sites,
-                                                           double *__restrict__ partials) {
+                                                           int dir, double *__restrict__ partials) {
     const CfgDesc &c = cfgs[ci];   // read in place (c.d is indexed at run time)
     const int s = blockIdx.y;
-    const int dd = c.d[dir];
-    const int S = c.V / dd;
+    const int S = c.V / c.d[dir];
     // the other three directions, increasing
     const int o0 = dir == 0 ? 1 : 0;
     const int o1 = dir <= 1 ? 2 : 1;
@@ -760,33 +759,24 @@ __global__ __launch_bounds__(256) void slice_charge_kernel(const CfgDesc *__rest
     auto stride_of = [&](int m) {
         return m == 0 ? 1 : m == 1 ? c.d[0] : m == 2 ? c.d[0] * c.d[1] : c.d[0] * c.d[1] * c.d[2];
     };
-    const int sa = stride_of(o0), sb = stride_of(o1), sc = stride_of(o2), sd = stride_of(dir);
-    const int da = c.d[o0], db = c.d[o1];
-    const Links<R, NE> W{as_global<R>((const void *)(c.cur ? c.W[1] : c.W[0])), c.stride};
-    double acc = 0;
-    const int j0 = blockIdx.x * chunk_sites;
-    const int j1 = min(j0 + chunk_sites, S);
-#pragma unroll 1
-    for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) {
+    double q = 0;
+    const int j = blockIdx.x * 256 + (int)threadIdx.x;
+    if (j < S) {
+        const int da = c.d[o0], db = c.d[o1];
         const int na = j % da, r = j / da;
         const int nb = r % db, nc = r / db;
-        const int i = na * sa + nb * sb + nc * sc + s * sd;
+        const int i = na * stride_of(o0) + nb * stride_of(o1) + nc * stride_of(o2) + s * stride_of(dir);
+        const Links<R, NE> W{as_global<R>((const void *)(c.cur ? c.W[1] : c.W[0])), c.stride};
         const Geo g = make_geo(c, i);
-        double v[4];   // lanes do not hold consecutive sites: leaves formed link by link
-        // the fences keep the three plane pairs from being interleaved (without
-        // them the kernel needs every register and spills)
-        measure_pair<R, 0>(W, c, g, v);
-        acc += v[1];
-        __builtin_amdgcn_sched_barrier(0);
-        measure_pair<R, 1>(W, c, g, v);
-        acc += v[1];
-        __builtin_amdgcn_sched_barrier(0);
-        measure_pair<R, 2>(W, c, g, v);
-        acc += v[1];
+        double v0[4], v1[4], v2[4];   // lanes do not hold consecutive sites: leaves formed link by link
+        measure_pair<R, 0>(W, c, g, v0);
+        measure_pair<R, 1>(W, c, g, v1);
+        measure_pair<R, 2>(W, c, g, v2);
+        q = (v0[1] + v1[1]) + v2[1];
     }
-    acc = wave_sum(acc);
+    q = wave_sum(q);
     __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
     __syncthreads();
     if (threadIdx.x == 0)
         partials[(size_t)s * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
@@ -1203,18 +1193,17 @@ hipError_t launch_check_final(hipStream_t s, const double *partials, int ntiles,
 hipError_t launch_slice_charge(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs, int ci,
                                int dir, int n_slices, int slice_sites, double *partials,
                                double *out) {
-    const int chunk = 1024;
-    const int chunks = (slice_sites + chunk - 1) / chunk;
+    const int chunks = (slice_sites + 255) / 256;
     dim3 grid(chunks, n_slices);
     if (p == P_F64)
         hipLaunchKernelGGL((slice_charge_kernel<double, 9>), grid, dim3(256), 0, s, cfgs, ci, dir,
-                           chunk, partials);
+                           partials);
     else if (c12)
         hipLaunchKernelGGL((slice_charge_kernel<float, 6>), grid, dim3(256), 0, s, cfgs, ci, dir,
-                           chunk, partials);
+                           partials);
     else
         hipLaunchKernelGGL((slice_charge_kernel<float, 9>), grid, dim3(256), 0, s, cfgs, ci, dir,
-                           chunk, partials);
+                           partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(slice_finalize_kernel, dim3((n_slices + 63) / 64), dim3(64), 0, s, partials,

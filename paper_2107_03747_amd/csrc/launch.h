@@ -73,7 +73,7 @@ hipError_t launch_check(Prec p, bool c12, hipStream_t s, const void *src, int V,
                         double *partials, double *out);
 
 // Topological charge per slice of direction `dir` for config ci (exec-order
-// descriptor at cfgs[ci]); partials need n_slices * ceil(slice_sites/1024)
+// descriptor at cfgs[ci]); partials need n_slices * ceil(slice_sites/256)
 // doubles, out n_slices doubles.
 hipError_t launch_slice_charge(Prec p, bool c12, hipStream_t s, const CfgDesc *cfgs, int ci,
                                int dir, int n_slices, int slice_sites, double *partials,
